@@ -1,0 +1,74 @@
+"""Pins for the AMS oracle: selection rules by construction, unbiasedness on OU."""
+import math
+
+import numpy as np
+
+from oracle import ams, ou
+
+
+def test_kill_branch_rules():
+    series = np.array([[0.0, 1.0, 0.5],    # max 1.0
+                       [0.0, 0.2, 0.1],    # max 0.2  <- lowest
+                       [0.3, 0.9, 2.0],    # max 2.0
+                       [0.2, 0.2, 0.0],    # max 0.2  <- tie with slot 1
+                       [np.nan, 5.0, 5.0]])  # non-finite -> -inf, killed first
+    kb = ams.kill_branch(series, n_kill=2, key=1, iteration=0)
+    assert kb.level == 0.2 and not kb.extinct
+    assert kb.killed.tolist() == [1, 3, 4]
+    for p, tb in zip(kb.parents, kb.branch_t):
+        assert p in (0, 2)
+        row = series[p]
+        assert row[tb] > 0.2 and np.all(row[:tb] <= 0.2)
+
+
+def test_extinction_when_all_equal():
+    kb = ams.kill_branch(np.ones((4, 3)), 1, 0, 0)
+    assert kb.extinct and len(kb.killed) == 4
+
+
+def test_parent_choice_uniform_over_survivors():
+    series = np.array([[float(i)] * 2 for i in range(6)])
+    counts = np.zeros(6)
+    for it in range(600):
+        kb = ams.kill_branch(series, 2, 7, it)
+        counts += np.bincount(kb.parents, minlength=6)
+    assert counts[0] == 0 and counts[1] == 0
+    exp = counts.sum() / 4
+    assert ((counts[2:] - exp) ** 2 / exp).sum() < 20
+
+
+def test_estimator_without_iterations_is_direct_sampling():
+    q = np.array([0.1, 0.5, 0.7, 2.0])
+    assert np.allclose(ams.estimate([], 4, q, np.array([0.5, 1.0])), [0.75, 0.25])
+    assert np.allclose(ams.estimate([1, 2], 4, q, np.array([0.0])), [0.75 * 0.5])
+
+
+def test_ams_unbiased_on_ou():
+    """Mean AMS estimate of P(max_[0,T_a] x >= a) equals brute-force Monte Carlo."""
+    dt, n_steps, a = 0.02, 100, 1.2
+    t_a = n_steps * dt
+    rng = np.random.default_rng(0)
+    x0 = ou.stationary(200_000, rng)
+    brute = (ou.paths(x0, n_steps, dt, rng).max(axis=1) >= a).mean()
+
+    def make_resim(rng):
+        def resim(parent, tb, slot, it):
+            tail = ou.paths(np.array([parent[tb]]), n_steps - tb - 1, dt, rng)[0]
+            return np.concatenate([parent[:tb + 1], tail])
+        return resim
+
+    est = []
+    for rep in range(120):
+        rng = np.random.default_rng(1000 + rep)
+        paths = ou.paths(ou.stationary(16, rng), n_steps, dt, rng)
+        res = ams.run(paths, make_resim(rng), n_kill=1, key=rep, max_iter=400, threshold=a)
+        assert not res["extinct"]
+        est.append(ams.estimate(res["k_history"], 16, ams.clean_maxima(res["paths"]), np.array([a]))[0])
+    mean, se = np.mean(est), np.std(est, ddof=1) / math.sqrt(len(est))
+    assert abs(mean - brute) < 4 * se + 0.003, (mean, brute, se)
+    assert brute < 0.3  # the level is not typical
+
+
+def test_return_time_formula_limits():
+    r = ams.return_time(np.array([0.0, 1e-9]), 5.0)
+    assert r[0] == math.inf and math.isclose(r[1] * 1e-9 / 5.0, 1.0, rel_tol=1e-8)
