@@ -1,0 +1,239 @@
+/*
+ * lbm.h -- C ABI of the MI355X ensemble lattice-Boltzmann + rare-event library.
+ *
+ * An ensemble of independent trajectories of a 2-D channel flow past a square
+ * (paper Section 2) is advanced by a D2Q9 lattice-BGK scheme (paper Appendix
+ * A) while the drag on the square is recorded every step (paper Section 2.1).
+ * The GKTL algorithm (paper Section 4.2, Appendix C) and trajectory AMS (paper
+ * Section 4.1, Appendix B) clone and prune the trajectories; branched copies
+ * are perturbed as in paper Appendix D.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Lattice units (dx = dt = 1, c_s^2 = 1/3).  Directions c_0..c_8 are
+ *   (0,0), (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1);
+ *   weights 4/9, 1/9 (x4), 1/36 (x4).
+ * - Geometry: ny fluid rows between halfway bounce-back walls at y = 0 and
+ *   y = ny, periodic in x.  The square with side s and lower-left cell
+ *   (sq_x0, sq_y0) is solid on cells sq_x0..sq_x0+s-1, sq_y0..sq_y0+s-1 and
+ *   must keep one fluid cell to every side: 1 <= sq_x0, sq_x0 + s <= nx - 1,
+ *   1 <= sq_y0, sq_y0 + s <= ny - 1.  s = 0 means no obstacle.
+ * - Populations are stored as FP32 deviations d_i = f_i - w_i from the
+ *   rest state, structure-of-arrays: member m occupies 9*nx*ny floats
+ *   starting at the sum of 9*nx*ny over members 0..m-1, laid out
+ *   [i][y][x] with x fastest.  What is stored for step t is the
+ *   post-collision state f_i^out(t); streaming happens when step t+1 reads
+ *   it.  Solid cells are never read or written.
+ * - Time: lbm_init produces step 0 (equilibrium at rest with the seeded
+ *   density, relaxed once) and its drag; each step of lbm_step_batch
+ *   produces the next step and its drag.  The drag of step t is written at
+ *   column t of the member's row of the drag series.
+ * - Collision: BGK, d_i <- d_i + (d_i^eq - d_i)/tau + F_i, with Guo's body
+ *   force (u = (sum c_i f_i + F/2)/rho; F_i = (1 - 1/(2 tau)) w_i
+ *   [3 (c_i - u) + 9 (c_i.u) c_i].F).  The paper prints the relaxation without
+ *   its leading f_i term; this is the standard form its viscosity relation
+ *   nu = (tau - 1/2)/3 belongs to.
+ * - Drag (x-force on the square) by momentum exchange: the sum over fluid
+ *   cells x and directions i with x + c_i in the square of 2 c_ix f_i^out(x).
+ * - Random numbers: Philox4x64-10 (Salmon et al., SC'11).  Key = (seed or
+ *   key, purpose), purpose tags INIT 0x494E4954, GKTS 0x474B5453,
+ *   PRTB 0x50525442, AMSP 0x414D5350; the counter and word used by each
+ *   draw are given with the call that makes it.  A word w becomes the
+ *   uniform (w >> 11) * 2^-53, or the index floor(w * n / 2^64).
+ * - Streams: every call that takes or owns a hipStream_t enqueues its work
+ *   on it and returns without waiting, unless its comment says otherwise.
+ * - Memory: every large buffer is owned by the caller and passed as a
+ *   device pointer; the library never frees caller memory.  The library
+ *   allocates its own small device scratch (per-member bookkeeping, drag
+ *   partial sums) in lbm_create and frees it in lbm_destroy.
+ * - Errors: every call returns LBM_OK (0) or a negative code; the message
+ *   of the last failure on the calling thread is lbm_last_error().  Argument
+ *   errors are detected before any work is enqueued.
+ * - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MI355X_LBM_H
+#define MI355X_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)       /* bad argument (sizes, geometry, tau <= 1/2, null pointer) */
+#define LBM_EHIP (-2)         /* a HIP runtime call failed */
+#define LBM_ERANGE (-3)       /* drag-series capacity would be exceeded */
+#define LBM_EUNSUPPORTED (-4) /* valid request the library does not implement */
+#define LBM_ENONFINITE (-5)   /* every trajectory has a non-finite weight */
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* One trajectory: lattice size, obstacle, relaxation time and body force. */
+typedef struct {
+    int32_t nx, ny;            /* lattice cells; nx >= 4, ny >= 4 */
+    int32_t sq_x0, sq_y0;      /* lower-left solid cell of the square */
+    int32_t sq_side;           /* side s in cells, 0 = no obstacle */
+    int32_t reserved;          /* must be 0 */
+    double tau;                /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3) */
+    double force_x;            /* body-force density along x (lattice units) */
+} lbm_member_desc;
+
+/* Floats one population buffer must hold for this ensemble (sum of 9*nx*ny). */
+size_t lbm_state_floats(const lbm_member_desc* members, int32_t n_members);
+
+/*
+ * Create a context for n_members trajectories.
+ *   pop_a, pop_b   caller-owned device buffers of pop_floats floats each
+ *                  (>= lbm_state_floats); states ping-pong between them.
+ *   drag_series    caller-owned device float[n_members][series_capacity];
+ *                  drag of step t goes to [m][t].
+ *   accum          caller-owned device double[n_members]: running
+ *                  sum over steps of (f_d - mu)/sigma * dt (lbm_set_observable),
+ *                  the time integral of the observable that GKTL weighs.
+ *   hip_stream     hipStream_t every call of this context enqueues on
+ *                  (NULL = the null stream).
+ * Returns LBM_EINVAL on bad geometry or sizes.  Does not touch the buffers.
+ */
+int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t n_members,
+               float* pop_a, float* pop_b, size_t pop_floats,
+               float* drag_series, int32_t series_capacity, double* accum,
+               void* hip_stream);
+
+/* Release the context and the library's own scratch (not the caller's buffers). */
+int lbm_destroy(lbm_ctx* ctx);
+
+/*
+ * Step 0 of every member (paper Section 2: equilibrium start).  Cell (x, y)
+ * of member m gets density rho = 1 + noise_amp * (2u - 1), u from Philox
+ * key (seed, INIT), counter (y*nx + x, m, 0, 0), word 0; populations are the
+ * equilibrium at rest f_i = w_i rho, relaxed once (collision with the body
+ * force).  Writes the drag of step 0 at column 0, zeroes accum and the
+ * non-finite flags, and activates every member.
+ */
+int lbm_init(lbm_ctx* ctx, uint64_t seed, double noise_amp);
+
+/* Observable weighed by GKTL: A(t) = (f_d(t) - mu)/sigma, integrated with step dt. */
+int lbm_set_observable(lbm_ctx* ctx, double mu, double sigma, double dt);
+
+/*
+ * Choose which members lbm_step_batch advances (host int32[n_members], nonzero
+ * = active; NULL = all).  An inactive member keeps its state, drag columns
+ * and accumulator untouched, and its own step counter stops.
+ */
+int lbm_set_active(lbm_ctx* ctx, const int32_t* active_host);
+
+/*
+ * Advance every active member by n_steps steps (paper Appendix A: stream,
+ * then collide), recording each step's drag in the member's next column and
+ * adding (f_d - mu)/sigma * dt to accum.  A member whose drag becomes
+ * non-finite is flagged (lbm_flags).  LBM_ERANGE if an active member would
+ * pass series_capacity.
+ */
+int lbm_step_batch(lbm_ctx* ctx, int32_t n_steps);
+
+/* Copy drag columns [t0, t1) of every member into out_dev (device float[n][t1-t0]). */
+int lbm_drag(const lbm_ctx* ctx, int32_t t0, int32_t t1, float* out_dev);
+
+/* Device pointer to member m's current state ([9][ny][nx] deviations). */
+int lbm_member_state(const lbm_ctx* ctx, int32_t m, float** state_dev);
+
+/* Next drag column (= number of steps taken, step 0 included) of member m. */
+int lbm_member_time(const lbm_ctx* ctx, int32_t m, int32_t* t);
+
+/* Set every member's next drag column to t (reuse the series buffer). */
+int lbm_set_time(lbm_ctx* ctx, int32_t t);
+
+/* Copy the non-finite flags into out_dev (device int32[n_members]): 1 where a
+   member's drag has become non-finite since lbm_init. */
+int lbm_flags(const lbm_ctx* ctx, int32_t* out_dev);
+
+/*
+ * Tile shape of the step kernel (an index into the library's table of
+ * shapes; see lbm_tile_count).  Every shape computes bit-identical results.
+ */
+int lbm_set_tile(lbm_ctx* ctx, int32_t tile_id);
+int32_t lbm_tile_count(void);
+/* Time every tile shape on this ensemble (n_steps each, on the context's
+   stream, synchronising it) and keep the fastest.  Writes the chosen id. */
+int lbm_autotune(lbm_ctx* ctx, int32_t n_steps, int32_t* best_tile);
+
+/*
+ * GKTL cloning at the end of a period (paper Appendix C.1, weight equation;
+ * Appendix D, perturbation).  All members must share one lattice shape.
+ *   s_n = k * accum[n]; ln R = ln((1/N) sum_n exp(s_n)) in FP64 with the
+ *   largest s_n factored out; ln R goes to ln_r_dev[0] (device double).
+ *   Multinomial resampling: new slot m takes ancestor a_m, the first n
+ *   whose running sum C_n = sum_{l<=n} exp(s_l - s_max) (index order)
+ *   exceeds u_m * C_{N-1}, u_m from key (key, GKTS), counter (m, period, 0, 0),
+ *   word 0.  Non-finite s_n has weight 0.  ancestors_dev (device int32[N])
+ *   receives a_m.  Every member's state becomes its ancestor's.  The lowest
+ *   slot taking each ancestor is an exact copy; every other copy is
+ *   perturbed: f <- f + eps * sum_n alpha_n f^(n) with alpha_n from key
+ *   (key, PRTB), counter (m, period, n / 4, 0), word n % 4, then scaled by
+ *   one factor that restores its mass before perturbation.
+ *   snapshots: device, n_snap states in this library's deviation layout
+ *   ([n_snap][9][ny][nx]); may be NULL when eps == 0 or n_snap == 0.
+ *   accum is reset to 0; flags are copied from the ancestor.
+ * LBM_ENONFINITE if every s_n is non-finite (nothing is changed).
+ */
+int gktl_select_clone(lbm_ctx* ctx, double k, uint64_t key, int32_t period,
+                      double eps, const float* snapshots, int32_t n_snap,
+                      int32_t* ancestors_dev, double* ln_r_dev);
+
+/*
+ * Perturb selected members in place (paper Appendix D) without cloning:
+ * member m with mask_host[m] != 0 gets f <- f + eps * sum_n alpha_n f^(n),
+ * alphas from key (key, PRTB), counter (m, period, n / 4, 0), word n % 4,
+ * then the scale that restores its mass.  Used at AMS branching points.
+ */
+int lbm_perturb(lbm_ctx* ctx, const int32_t* mask_host, uint64_t key, int32_t period,
+                double eps, const float* snapshots, int32_t n_snap);
+
+/*
+ * Copy states between members of this context and external device buffers
+ * (checkpoints).  lbm_copy_state_out writes member m's current state into
+ * dst_dev ([9][ny][nx] floats); lbm_copy_state_in makes src_dev the current
+ * state of member m and sets its next drag column to t.
+ */
+int lbm_copy_state_out(const lbm_ctx* ctx, int32_t m, float* dst_dev);
+int lbm_copy_state_in(lbm_ctx* ctx, int32_t m, const float* src_dev, int32_t t);
+
+/*
+ * Trajectory-AMS selection (paper Section 4.1; Appendix B.1).  Independent of
+ * any context: works on N score series of length t_len (device float[N][t_len],
+ * row-major).  The maximum of each row (rows holding a non-finite value count
+ * as -inf) goes to maxima_dev (device float[N]).  The level is the n_kill-th
+ * lowest maximum; every member at or below it is killed (ties together), in
+ * increasing slot order, into killed_dev[0..K-1].  Kill j picks its parent
+ * uniformly among the survivors (increasing slot order) with index
+ * floor(w * n_surv / 2^64), w from key (key, AMSP), counter (j, iteration, 0, 0),
+ * word 0, into parent_dev[j]; branch_t_dev[j] is the first column where the
+ * parent's score is strictly above the level.  n_killed_dev (device int32)
+ * receives K, level_dev (device float) the level.  If every member is at the
+ * level (extinction) K = N and parents/branch times are -1.
+ */
+int ams_score_kill_branch(const float* series_dev, int32_t n, int32_t t_len, int32_t n_kill,
+                          uint64_t key, int32_t iteration,
+                          int32_t* killed_dev, int32_t* parent_dev, int32_t* branch_t_dev,
+                          int32_t* n_killed_dev, float* level_dev, float* maxima_dev,
+                          void* hip_stream);
+
+/*
+ * Window mean of each member's drag series (paper Section 3.2, time-averaged
+ * drag): out_dev[m][t] = (1/T) sum_{t' = t-T+1}^{t} f_d(t') for t >= T-1 within
+ * [0, t_len) of the device series (float[n][ld]), and -inf for t < T-1.
+ * Sums in FP64.  Used as the plain AMS score.
+ */
+int lbm_window_mean(const float* series_dev, int32_t n, int32_t ld, int32_t t_len, int32_t window,
+                    float* out_dev, void* hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355X_LBM_H */

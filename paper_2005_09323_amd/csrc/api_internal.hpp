@@ -1,0 +1,61 @@
+// Host-side context of the C ABI and helpers shared by the API sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+namespace lbm {
+
+constexpr int MAX_MEMBERS = 4096;
+constexpr int DEFAULT_TILE = 1;
+
+struct MaskBits {
+    unsigned w[MAX_MEMBERS / 32];
+};
+
+hipError_t fill_int(int* p, int n, int v, hipStream_t st);
+hipError_t fill_double(double* p, int n, double v, hipStream_t st);
+hipError_t set_int(int* p, int v, hipStream_t st);
+hipError_t set_bits(int* p, int n, const MaskBits& bits, hipStream_t st);
+
+}  // namespace lbm
+
+struct lbm_ctx {
+    int n = 0;
+    std::vector<lbm_member_desc> desc;
+    std::vector<lbm::MemberDev> h_members;
+    lbm::MemberDev* d_members = nullptr;
+    float* pop[2] = {nullptr, nullptr};
+    size_t pop_floats = 0;
+    float* series = nullptr;
+    int cap = 0;
+    double* accum = nullptr;
+    hipStream_t stream = nullptr;
+    // per-member bookkeeping; the host mirrors change in lockstep with the
+    // device copies (same calls, same order), so no read-back is needed
+    int* d_parity = nullptr;
+    int* d_cursor = nullptr;
+    int* d_active = nullptr;
+    int* d_flags = nullptr;
+    std::vector<int> h_parity, h_cursor, h_active;
+    double* d_partial = nullptr;
+    long long partial_floats = 0;
+    double* d_scratch = nullptr;  // FP64 scratch for selection / mass sums
+    int* d_iscratch = nullptr;    // int scratch for selection
+    long long max_cells = 0;
+    bool uniform_shape = true;
+    int chunk = 64;
+    double mu = 0.0, sigma = 1.0, dt = 1.0;
+    int tile_id = lbm::DEFAULT_TILE;
+    int xcd_remap = 1;
+    int nseg = 0;
+    int total_blocks = 0;
+    lbm::Segment seg[lbm::MAX_SEGMENTS];
+};
+
+int lbm_fail(int code, const char* fmt, ...);
+int lbm_hip_fail(hipError_t e, const char* what);

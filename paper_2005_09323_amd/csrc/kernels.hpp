@@ -1,0 +1,71 @@
+// Kernel argument blocks and launchers shared between the kernel sources and
+// the C-ABI layer.
+#pragma once
+
+#include "common.hpp"
+
+namespace lbm {
+
+constexpr int MAX_SEGMENTS = 32;  // runs of consecutive members with one lattice shape
+constexpr int MAX_CHUNK = 256;    // steps per drag-reduction chunk
+
+struct Segment {
+    int block_begin;       // first workgroup of the segment
+    int member_begin;      // first member
+    int tiles_per_member;  // tiles_x * tiles_y
+    int tiles_x;
+};
+
+struct StepArgs {
+    const MemberDev* members;
+    const int* parity;   // per member: which buffer holds its state before this chunk
+    const int* active;
+    float* pop0;
+    float* pop1;
+    double* partial;     // drag partials [member][slot][ring]
+    int slot;            // step index within the chunk
+    int flip;            // slot & 1: parity of this step relative to the chunk start
+    int xcd;             // remap workgroups so each XCD gets contiguous tiles
+    int total_blocks;
+    int nseg;
+    Segment seg[MAX_SEGMENTS];
+};
+
+struct InitArgs {
+    const MemberDev* members;
+    float* pop0;
+    double* partial;
+    uint64_t seed;
+    double noise_amp;
+};
+
+struct FinalizeArgs {
+    const MemberDev* members;
+    const int* active;
+    int* parity;
+    int* cursor;
+    int* flags;
+    const double* partial;
+    float* series;
+    double* accum;
+    long long ld;        // row stride of the drag series
+    int n;               // steps in this chunk
+    int accumulate;      // add the observable to accum (0 for step 0)
+    int advance_parity;  // 1: the chunk's steps ping-ponged the buffers; 0 for step 0
+    double mu;
+    double inv_sigma_dt; // dt / sigma
+};
+
+struct TileShape {
+    int tyt;  // thread rows per workgroup (workgroup = 64 x tyt threads)
+    int r;    // rows per thread
+};
+
+extern const TileShape TILE_SHAPES[];
+extern const int N_TILE_SHAPES;
+
+hipError_t launch_step(int tile_id, const StepArgs& a, hipStream_t st);
+hipError_t launch_init(const InitArgs& a, int n_members, long long max_cells, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs& a, int n_members, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,456 @@
+// C-ABI layer: context lifetime, argument validation, chunked stepping and
+// the bookkeeping mirrors the host keeps of per-member device state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "api_internal.hpp"
+
+using namespace lbm;
+
+static thread_local std::string g_last_error;
+
+int lbm_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int lbm_hip_fail(hipError_t e, const char* what) {
+    return lbm_fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// small device utilities
+
+namespace lbm {
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = v;
+}
+__global__ void fill_double_kernel(double* p, int n, double v) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = v;
+}
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+__global__ void set_bits_kernel(int* p, int n, MaskBits bits) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = (int)((bits.w[i >> 5] >> (i & 31)) & 1u);
+}
+
+hipError_t fill_int(int* p, int n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t fill_double(double* p, int n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_double_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t set_int(int* p, int v, hipStream_t st) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, p, v);
+    return hipGetLastError();
+}
+hipError_t set_bits(int* p, int n, const MaskBits& bits, hipStream_t st) {
+    hipLaunchKernelGGL(set_bits_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, bits);
+    return hipGetLastError();
+}
+
+}  // namespace lbm
+
+// ---------------------------------------------------------------------------
+
+static long long member_floats(const lbm_member_desc& d) { return 9LL * d.nx * d.ny; }
+
+extern "C" size_t lbm_state_floats(const lbm_member_desc* members, int32_t n) {
+    if (!members || n <= 0) return 0;
+    size_t tot = 0;
+    for (int i = 0; i < n; ++i) tot += (size_t)member_floats(members[i]);
+    return tot;
+}
+
+static int validate_member(const lbm_member_desc& d, int i) {
+    if (d.nx < 4 || d.ny < 4) return lbm_fail(LBM_EINVAL, "member %d: nx, ny must be >= 4", i);
+    if ((long long)d.nx * d.ny > (1LL << 30)) return lbm_fail(LBM_EINVAL, "member %d: lattice too large", i);
+    if (d.reserved != 0) return lbm_fail(LBM_EINVAL, "member %d: reserved field must be 0", i);
+    if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return lbm_fail(LBM_EINVAL, "member %d: tau must be > 1/2", i);
+    if (!std::isfinite(d.force_x)) return lbm_fail(LBM_EINVAL, "member %d: force must be finite", i);
+    if (d.sq_side < 0) return lbm_fail(LBM_EINVAL, "member %d: negative square side", i);
+    if (d.sq_side > 0) {
+        if (d.sq_x0 < 1 || d.sq_x0 + d.sq_side > d.nx - 1 || d.sq_y0 < 1 || d.sq_y0 + d.sq_side > d.ny - 1)
+            return lbm_fail(LBM_EINVAL, "member %d: square must keep one fluid cell on every side", i);
+    }
+    return LBM_OK;
+}
+
+// Build the segment table of the current tile shape: runs of consecutive
+// members with the same lattice shape share a tiling.
+static int build_segments(lbm_ctx* c) {
+    const TileShape ts = TILE_SHAPES[c->tile_id];
+    const int rows = ts.tyt * ts.r;
+    c->nseg = 0;
+    int blocks = 0;
+    for (int m = 0; m < c->n; ++m) {
+        const auto& d = c->desc[m];
+        const bool same = c->nseg > 0 && c->desc[c->seg[c->nseg - 1].member_begin].nx == d.nx &&
+                          c->desc[c->seg[c->nseg - 1].member_begin].ny == d.ny;
+        const int tx = (d.nx + 63) / 64, ty = (d.ny + rows - 1) / rows;
+        if (!same) {
+            if (c->nseg == MAX_SEGMENTS)
+                return lbm_fail(LBM_EUNSUPPORTED, "more than %d runs of distinct lattice shapes; group members by shape",
+                                MAX_SEGMENTS);
+            Segment s;
+            s.block_begin = blocks;
+            s.member_begin = m;
+            s.tiles_per_member = tx * ty;
+            s.tiles_x = tx;
+            c->seg[c->nseg++] = s;
+        }
+        if ((long long)blocks + (long long)tx * ty > (1LL << 31) - 1)
+            return lbm_fail(LBM_EUNSUPPORTED, "ensemble needs more than 2^31 workgroups");
+        blocks += tx * ty;
+    }
+    c->total_blocks = blocks;
+    return LBM_OK;
+}
+
+extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t n_members, float* pop_a,
+                          float* pop_b, size_t pop_floats, float* drag_series, int32_t series_capacity,
+                          double* accum, void* hip_stream) {
+    if (!out) return lbm_fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!members || n_members <= 0) return lbm_fail(LBM_EINVAL, "need at least one member");
+    if (n_members > MAX_MEMBERS) return lbm_fail(LBM_EINVAL, "at most %d members", MAX_MEMBERS);
+    if (!pop_a || !pop_b || !drag_series || !accum) return lbm_fail(LBM_EINVAL, "NULL device buffer");
+    if (pop_a == pop_b) return lbm_fail(LBM_EINVAL, "pop_a and pop_b must be distinct buffers");
+    if (series_capacity < 1) return lbm_fail(LBM_EINVAL, "series_capacity must be >= 1");
+    for (int i = 0; i < n_members; ++i) {
+        int rc = validate_member(members[i], i);
+        if (rc) return rc;
+    }
+    const size_t need = lbm_state_floats(members, n_members);
+    if (pop_floats < need) return lbm_fail(LBM_EINVAL, "population buffers hold %zu floats, need %zu", pop_floats, need);
+
+    lbm_ctx* c = new lbm_ctx();
+    c->n = n_members;
+    c->desc.assign(members, members + n_members);
+    c->pop[0] = pop_a;
+    c->pop[1] = pop_b;
+    c->pop_floats = pop_floats;
+    c->series = drag_series;
+    c->cap = series_capacity;
+    c->accum = accum;
+    c->stream = (hipStream_t)hip_stream;
+    c->h_parity.assign(n_members, 0);
+    c->h_cursor.assign(n_members, 0);
+    c->h_active.assign(n_members, 1);
+
+    long long off = 0, part = 0;
+    c->h_members.resize(n_members);
+    c->uniform_shape = true;
+    for (int i = 0; i < n_members; ++i) {
+        const auto& d = members[i];
+        MemberDev& m = c->h_members[i];
+        m.nx = d.nx;
+        m.ny = d.ny;
+        m.sx0 = d.sq_x0;
+        m.sy0 = d.sq_y0;
+        m.ss = d.sq_side;
+        m.ring = d.sq_side > 0 ? 4 * d.sq_side + 4 : 0;
+        const double omega = 1.0 / d.tau;
+        m.omega = omega;
+        m.half_fx = 0.5 * d.force_x;
+        m.gf3 = (1.0 - 0.5 * omega) * 3.0 * d.force_x;
+        m.gf9 = (1.0 - 0.5 * omega) * 9.0 * d.force_x;
+        m.off = off;
+        m.part_off = part;
+        off += member_floats(d);
+        part += (long long)m.ring * MAX_CHUNK;
+        c->max_cells = std::max<long long>(c->max_cells, (long long)d.nx * d.ny);
+        if (d.nx != members[0].nx || d.ny != members[0].ny) c->uniform_shape = false;
+    }
+    c->partial_floats = std::max<long long>(part, 1);
+    c->tile_id = DEFAULT_TILE;
+    int rc = build_segments(c);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+
+    hipError_t e;
+    if ((e = hipMalloc(&c->d_members, sizeof(MemberDev) * n_members)) != hipSuccess ||
+        (e = hipMalloc(&c->d_parity, sizeof(int) * n_members)) != hipSuccess ||
+        (e = hipMalloc(&c->d_cursor, sizeof(int) * n_members)) != hipSuccess ||
+        (e = hipMalloc(&c->d_active, sizeof(int) * n_members)) != hipSuccess ||
+        (e = hipMalloc(&c->d_flags, sizeof(int) * n_members)) != hipSuccess ||
+        (e = hipMalloc(&c->d_partial, sizeof(double) * c->partial_floats)) != hipSuccess ||
+        (e = hipMalloc(&c->d_scratch, sizeof(double) * (4 * (size_t)n_members + 64))) != hipSuccess ||
+        (e = hipMalloc(&c->d_iscratch, sizeof(int) * (4 * (size_t)n_members + 64))) != hipSuccess) {
+        lbm_destroy(c);
+        return lbm_hip_fail(e, "hipMalloc of library scratch");
+    }
+    if ((e = hipMemcpy(c->d_members, c->h_members.data(), sizeof(MemberDev) * n_members, hipMemcpyHostToDevice)) !=
+        hipSuccess) {
+        lbm_destroy(c);
+        return lbm_hip_fail(e, "upload of member table");
+    }
+    if ((e = fill_int(c->d_parity, n_members, 0, c->stream)) != hipSuccess ||
+        (e = fill_int(c->d_cursor, n_members, 0, c->stream)) != hipSuccess ||
+        (e = fill_int(c->d_active, n_members, 1, c->stream)) != hipSuccess ||
+        (e = fill_int(c->d_flags, n_members, 0, c->stream)) != hipSuccess) {
+        lbm_destroy(c);
+        return lbm_hip_fail(e, "initialising bookkeeping");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" int lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
+    hipFree(c->d_members);
+    hipFree(c->d_parity);
+    hipFree(c->d_cursor);
+    hipFree(c->d_active);
+    hipFree(c->d_flags);
+    hipFree(c->d_partial);
+    hipFree(c->d_scratch);
+    hipFree(c->d_iscratch);
+    delete c;
+    return LBM_OK;
+}
+
+static FinalizeArgs finalize_args(lbm_ctx* c, int n, int accumulate, int advance) {
+    FinalizeArgs f;
+    f.members = c->d_members;
+    f.active = c->d_active;
+    f.parity = c->d_parity;
+    f.cursor = c->d_cursor;
+    f.flags = c->d_flags;
+    f.partial = c->d_partial;
+    f.series = c->series;
+    f.accum = c->accum;
+    f.ld = c->cap;
+    f.n = n;
+    f.accumulate = accumulate;
+    f.advance_parity = advance;
+    f.mu = c->mu;
+    f.inv_sigma_dt = c->dt / c->sigma;
+    return f;
+}
+
+extern "C" int lbm_init(lbm_ctx* c, uint64_t seed, double noise_amp) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (!std::isfinite(noise_amp) || noise_amp < 0 || noise_amp >= 0.5)
+        return lbm_fail(LBM_EINVAL, "noise_amp must be in [0, 0.5)");
+    hipError_t e;
+    if ((e = fill_int(c->d_parity, c->n, 0, c->stream)) != hipSuccess ||
+        (e = fill_int(c->d_cursor, c->n, 0, c->stream)) != hipSuccess ||
+        (e = fill_int(c->d_active, c->n, 1, c->stream)) != hipSuccess ||
+        (e = fill_int(c->d_flags, c->n, 0, c->stream)) != hipSuccess ||
+        (e = fill_double(c->accum, c->n, 0.0, c->stream)) != hipSuccess)
+        return lbm_hip_fail(e, "lbm_init bookkeeping");
+    std::fill(c->h_parity.begin(), c->h_parity.end(), 0);
+    std::fill(c->h_active.begin(), c->h_active.end(), 1);
+    InitArgs a;
+    a.members = c->d_members;
+    a.pop0 = c->pop[0];
+    a.partial = c->d_partial;
+    a.seed = seed;
+    a.noise_amp = noise_amp;
+    if ((e = launch_init(a, c->n, c->max_cells, c->stream)) != hipSuccess) return lbm_hip_fail(e, "init kernel");
+    if ((e = launch_finalize(finalize_args(c, 1, 0, 0), c->n, c->stream)) != hipSuccess)
+        return lbm_hip_fail(e, "drag reduction");
+    std::fill(c->h_cursor.begin(), c->h_cursor.end(), 1);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_observable(lbm_ctx* c, double mu, double sigma, double dt) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (!std::isfinite(mu) || !(sigma > 0) || !std::isfinite(sigma) || !(dt > 0) || !std::isfinite(dt))
+        return lbm_fail(LBM_EINVAL, "need finite mu, sigma > 0, dt > 0");
+    c->mu = mu;
+    c->sigma = sigma;
+    c->dt = dt;
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_active(lbm_ctx* c, const int32_t* active_host) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    MaskBits bits{};
+    for (int m = 0; m < c->n; ++m) {
+        const int on = active_host ? (active_host[m] != 0) : 1;
+        c->h_active[m] = on;
+        if (on) bits.w[m >> 5] |= 1u << (m & 31);
+    }
+    hipError_t e = set_bits(c->d_active, c->n, bits, c->stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "active mask upload");
+}
+
+extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (n_steps < 0) return lbm_fail(LBM_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return LBM_OK;
+    for (int m = 0; m < c->n; ++m)
+        if (c->h_active[m] && (long long)c->h_cursor[m] + n_steps > c->cap)
+            return lbm_fail(LBM_ERANGE, "member %d: drag column %d + %d steps exceeds capacity %d", m,
+                            c->h_cursor[m], n_steps, c->cap);
+    StepArgs a;
+    a.members = c->d_members;
+    a.parity = c->d_parity;
+    a.active = c->d_active;
+    a.pop0 = c->pop[0];
+    a.pop1 = c->pop[1];
+    a.partial = c->d_partial;
+    a.xcd = c->xcd_remap;
+    a.total_blocks = c->total_blocks;
+    a.nseg = c->nseg;
+    for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
+    hipError_t e;
+    int done = 0;
+    while (done < n_steps) {
+        const int chunk = std::min(n_steps - done, c->chunk);
+        for (int s = 0; s < chunk; ++s) {
+            a.slot = s;
+            a.flip = s & 1;
+            if ((e = launch_step(c->tile_id, a, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
+        }
+        if ((e = launch_finalize(finalize_args(c, chunk, 1, 1), c->n, c->stream)) != hipSuccess)
+            return lbm_hip_fail(e, "drag reduction");
+        for (int m = 0; m < c->n; ++m)
+            if (c->h_active[m]) {
+                c->h_parity[m] ^= (chunk & 1);
+                c->h_cursor[m] += chunk;
+            }
+        done += chunk;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_drag(const lbm_ctx* c, int32_t t0, int32_t t1, float* out_dev) {
+    if (!c || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (t0 < 0 || t1 < t0 || t1 > c->cap) return lbm_fail(LBM_EINVAL, "bad column range [%d, %d)", t0, t1);
+    if (t1 == t0) return LBM_OK;
+    hipError_t e = hipMemcpy2DAsync(out_dev, sizeof(float) * (t1 - t0), c->series + t0, sizeof(float) * c->cap,
+                                    sizeof(float) * (t1 - t0), c->n, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "drag copy");
+}
+
+extern "C" int lbm_member_state(const lbm_ctx* c, int32_t m, float** state_dev) {
+    if (!c || !state_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (m < 0 || m >= c->n) return lbm_fail(LBM_EINVAL, "member %d out of range", m);
+    *state_dev = c->pop[c->h_parity[m]] + c->h_members[m].off;
+    return LBM_OK;
+}
+
+extern "C" int lbm_member_time(const lbm_ctx* c, int32_t m, int32_t* t) {
+    if (!c || !t) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (m < 0 || m >= c->n) return lbm_fail(LBM_EINVAL, "member %d out of range", m);
+    *t = c->h_cursor[m];
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_time(lbm_ctx* c, int32_t t) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (t < 0 || t > c->cap) return lbm_fail(LBM_EINVAL, "time %d outside [0, %d]", t, c->cap);
+    hipError_t e = fill_int(c->d_cursor, c->n, t, c->stream);
+    if (e != hipSuccess) return lbm_hip_fail(e, "cursor reset");
+    std::fill(c->h_cursor.begin(), c->h_cursor.end(), t);
+    return LBM_OK;
+}
+
+extern "C" int lbm_flags(const lbm_ctx* c, int32_t* out_dev) {
+    if (!c || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(out_dev, c->d_flags, sizeof(int) * c->n, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "flags copy");
+}
+
+extern "C" int32_t lbm_tile_count(void) { return N_TILE_SHAPES; }
+
+extern "C" int lbm_set_tile(lbm_ctx* c, int32_t tile_id) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (tile_id < 0 || tile_id >= N_TILE_SHAPES) return lbm_fail(LBM_EINVAL, "tile id %d out of range", tile_id);
+    const int old = c->tile_id;
+    c->tile_id = tile_id;
+    int rc = build_segments(c);
+    if (rc) {
+        c->tile_id = old;
+        build_segments(c);
+    }
+    return rc;
+}
+
+extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
+    if (!c || !best_tile) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (n_steps < 1) return lbm_fail(LBM_EINVAL, "n_steps must be >= 1");
+    StepArgs a;
+    a.members = c->d_members;
+    a.parity = c->d_parity;
+    a.active = c->d_active;
+    a.pop0 = c->pop[0];
+    a.pop1 = c->pop[1];
+    a.partial = c->d_partial;
+    a.xcd = c->xcd_remap;
+    // Steps are timed in pairs so every state ends in the buffer it started
+    // in; the states do advance (untracked: no drag, no cursor), so callers
+    // tune before lbm_init, which rebuilds step 0.
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return lbm_fail(LBM_EHIP, "event creation failed");
+    float best_ms = 1e30f;
+    int best = c->tile_id;
+    const int pairs = std::max(1, n_steps / 2);
+    for (int t = 0; t < N_TILE_SHAPES; ++t) {
+        c->tile_id = t;
+        if (build_segments(c) != LBM_OK) continue;
+        a.total_blocks = c->total_blocks;
+        a.nseg = c->nseg;
+        for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
+        a.slot = 0;
+        // warm-up pair
+        for (int s = 0; s < 2; ++s) {
+            a.flip = s;
+            launch_step(t, a, c->stream);
+        }
+        hipEventRecord(e0, c->stream);
+        for (int p = 0; p < pairs; ++p)
+            for (int s = 0; s < 2; ++s) {
+                a.flip = s;
+                launch_step(t, a, c->stream);
+            }
+        hipEventRecord(e1, c->stream);
+        hipError_t err = hipEventSynchronize(e1);
+        if (err != hipSuccess) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return lbm_hip_fail(err, "autotune timing");
+        }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tile_id = best;
+    build_segments(c);
+    *best_tile = best;
+    return LBM_OK;
+}

@@ -1,0 +1,175 @@
+"""Python face of the C ABI: an ensemble of channel-flow trajectories on one GPU.
+
+PyTorch provides the device memory (population buffers, drag series,
+accumulators) and the stream; every computation runs in the HIP library
+through ``native``.  Calls are asynchronous on the current torch stream
+unless stated otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import native
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Ensemble:
+    """Members (objects with nx, ny, tau, force_x, square) advanced together.
+
+    series_capacity: drag columns kept per member (step 0 included).
+    """
+
+    def __init__(self, members: Sequence, series_capacity: int, device: str = "cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the ensemble needs a GPU (HIP device)")
+        self.lib = native.lib()
+        self.members = list(members)
+        self.n = len(self.members)
+        self.device = torch.device(device)
+        self._descs = native.desc_array(self.members)
+        floats = self.lib.lbm_state_floats(self._descs, self.n)
+        self.pop_a = torch.empty(floats, dtype=torch.float32, device=self.device)
+        self.pop_b = torch.empty(floats, dtype=torch.float32, device=self.device)
+        self.series = torch.zeros((self.n, series_capacity), dtype=torch.float32, device=self.device)
+        self.accum = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        self.capacity = series_capacity
+        self.stream = stream
+        self._ctx = ctypes.c_void_p()
+        native.check(self.lib.lbm_create(ctypes.byref(self._ctx), self._descs, self.n, _ptr(self.pop_a),
+                                         _ptr(self.pop_b), floats, _ptr(self.series), series_capacity,
+                                         _ptr(self.accum), _stream_handle(stream)))
+        self.offsets = []
+        off = 0
+        for m in self.members:
+            self.offsets.append(off)
+            off += 9 * m.nx * m.ny
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self) -> None:
+        if self._ctx:
+            native.check(self.lib.lbm_destroy(self._ctx))
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping -----------------------------------------------------------
+    def init(self, seed: int, noise_amp: float) -> None:
+        native.check(self.lib.lbm_init(self._ctx, seed, noise_amp))
+
+    def step(self, n_steps: int) -> None:
+        native.check(self.lib.lbm_step_batch(self._ctx, n_steps))
+
+    def set_observable(self, mu: float, sigma: float, dt: float) -> None:
+        native.check(self.lib.lbm_set_observable(self._ctx, mu, sigma, dt))
+
+    def set_active(self, active: Optional[Sequence[int]]) -> None:
+        if active is None:
+            native.check(self.lib.lbm_set_active(self._ctx, None))
+            return
+        arr = (ctypes.c_int32 * self.n)(*[int(bool(a)) for a in active])
+        native.check(self.lib.lbm_set_active(self._ctx, arr))
+
+    def set_tile(self, tile_id: int) -> None:
+        native.check(self.lib.lbm_set_tile(self._ctx, tile_id))
+
+    def autotune(self, n_steps: int = 20) -> int:
+        best = ctypes.c_int32()
+        native.check(self.lib.lbm_autotune(self._ctx, n_steps, ctypes.byref(best)))
+        return best.value
+
+    def set_time(self, t: int) -> None:
+        native.check(self.lib.lbm_set_time(self._ctx, t))
+
+    # -- results ------------------------------------------------------------
+    def time(self, m: int = 0) -> int:
+        t = ctypes.c_int32()
+        native.check(self.lib.lbm_member_time(self._ctx, m, ctypes.byref(t)))
+        return t.value
+
+    def drag(self, t0: int = 0, t1: Optional[int] = None) -> torch.Tensor:
+        t1 = self.time(0) if t1 is None else t1
+        out = torch.empty((self.n, t1 - t0), dtype=torch.float32, device=self.device)
+        native.check(self.lib.lbm_drag(self._ctx, t0, t1, _ptr(out)))
+        return out
+
+    def state(self, m: int) -> torch.Tensor:
+        """View [9, ny, nx] of member m's current state (deviations f_i - w_i)."""
+        p = ctypes.c_void_p()
+        native.check(self.lib.lbm_member_state(self._ctx, m, ctypes.byref(p)))
+        mm = self.members[m]
+        base = self.pop_a if p.value - self.pop_a.data_ptr() in range(0, self.pop_a.numel() * 4) else self.pop_b
+        start = (p.value - base.data_ptr()) // 4
+        return base[start:start + 9 * mm.nx * mm.ny].view(9, mm.ny, mm.nx)
+
+    def flags(self) -> torch.Tensor:
+        """int32[N] on the device: 1 where a member's drag became non-finite."""
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        native.check(self.lib.lbm_flags(self._ctx, _ptr(out)))
+        return out
+
+    def copy_state_out(self, m: int, dst: torch.Tensor) -> None:
+        native.check(self.lib.lbm_copy_state_out(self._ctx, m, _ptr(dst)))
+
+    def copy_state_in(self, m: int, src: torch.Tensor, t: int) -> None:
+        native.check(self.lib.lbm_copy_state_in(self._ctx, m, _ptr(src), t))
+
+    # -- rare-event selection ----------------------------------------------
+    def gktl_select_clone(self, k: float, key: int, period: int, eps: float = 0.0,
+                          snapshots: Optional[torch.Tensor] = None):
+        """Returns (ancestors int32[N] device, ln R float64[1] device)."""
+        anc = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        lnr = torch.empty(1, dtype=torch.float64, device=self.device)
+        n_snap = 0 if snapshots is None else int(snapshots.shape[0])
+        native.check(self.lib.gktl_select_clone(self._ctx, k, key, period, eps, _ptr(snapshots), n_snap,
+                                                _ptr(anc), _ptr(lnr)))
+        return anc, lnr
+
+    def perturb(self, mask: Sequence[int], key: int, period: int, eps: float, snapshots: torch.Tensor) -> None:
+        arr = (ctypes.c_int32 * self.n)(*[int(bool(a)) for a in mask])
+        native.check(self.lib.lbm_perturb(self._ctx, arr, key, period, eps, _ptr(snapshots),
+                                          int(snapshots.shape[0])))
+
+
+def window_mean(series: torch.Tensor, window: int, t_len: Optional[int] = None) -> torch.Tensor:
+    """out[m, t] = mean of series[m, t-window+1 .. t] (FP64 sums), -inf before the first full window."""
+    n, ld = series.shape
+    t_len = ld if t_len is None else t_len
+    out = torch.empty((n, t_len), dtype=torch.float32, device=series.device)
+    native.check(native.lib().lbm_window_mean(_ptr(series), n, ld, t_len, window, _ptr(out),
+                                              _stream_handle(None)))
+    return out
+
+
+def ams_score_kill_branch(series: torch.Tensor, n_kill: int, key: int, iteration: int):
+    """AMS selection on score series [N, T]; returns a dict of device tensors and host values (synchronises)."""
+    n, t_len = series.shape
+    dev = series.device
+    killed = torch.empty(n, dtype=torch.int32, device=dev)
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    branch_t = torch.empty(n, dtype=torch.int32, device=dev)
+    n_killed = torch.empty(1, dtype=torch.int32, device=dev)
+    level = torch.empty(1, dtype=torch.float32, device=dev)
+    maxima = torch.empty(n, dtype=torch.float32, device=dev)
+    native.check(native.lib().ams_score_kill_branch(_ptr(series), n, t_len, n_kill, key, iteration,
+                                                    _ptr(killed), _ptr(parent), _ptr(branch_t),
+                                                    _ptr(n_killed), _ptr(level), _ptr(maxima),
+                                                    _stream_handle(None)))
+    k = int(n_killed.item())
+    return dict(killed=killed[:k], parents=parent[:k], branch_t=branch_t[:k], level=float(level.item()),
+                maxima=maxima, n_killed=k)

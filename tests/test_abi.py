@@ -1,0 +1,65 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching a GPU."""
+import ctypes
+
+import pytest
+
+import workloads
+from paper_2005_09323_amd import native
+
+
+def test_library_exports_every_declared_function():
+    lib = native.lib()
+    names = native.declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    for required in ("lbm_init", "lbm_step_batch", "lbm_drag", "gktl_select_clone", "ams_score_kill_branch"):
+        assert required in names
+
+
+def test_state_floats():
+    lib = native.lib()
+    wl = workloads.mixed_sizes(per_size=2)
+    arr = native.desc_array(wl.members)
+    assert lib.lbm_state_floats(arr, len(wl.members)) == sum(9 * m.nx * m.ny for m in wl.members)
+    assert lib.lbm_state_floats(None, 0) == 0
+
+
+def _create(members, pop_floats=10**9, cap=10, a=1, b=2, series=3, accum=4):
+    lib = native.lib()
+    ctx = ctypes.c_void_p()
+    arr = native.desc_array(members)
+    rc = lib.lbm_create(ctypes.byref(ctx), arr, len(members), a, b, pop_floats, series, cap, accum, None)
+    return rc, lib.lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("member,msg", [
+    (workloads.Member(64, 16, 0.5, 0.0, None), "tau"),
+    (workloads.Member(64, 16, 0.6, float("nan"), None), "force"),
+    (workloads.Member(2, 16, 0.6, 0.0, None), "nx"),
+    (workloads.Member(64, 16, 0.6, 0.0, (0, 4, 4)), "square"),
+    (workloads.Member(64, 16, 0.6, 0.0, (10, 4, 12)), "square"),
+    (workloads.Member(64, 16, 0.6, 0.0, (61, 4, 3)), "square"),
+])
+def test_create_rejects_bad_members(member, msg):
+    rc, err = _create([member])
+    assert rc == native.LBM_EINVAL and msg in err
+
+
+def test_create_rejects_bad_buffers():
+    m = workloads.Member(64, 16, 0.6, 0.0, (10, 4, 4))
+    assert _create([m], pop_floats=9 * 64 * 16 - 1)[0] == native.LBM_EINVAL
+    assert _create([m], a=0)[0] == native.LBM_EINVAL
+    assert _create([m], a=5, b=5)[0] == native.LBM_EINVAL
+    assert _create([m], cap=0)[0] == native.LBM_EINVAL
+    assert _create([])[0] == native.LBM_EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = native.lib()
+    assert lib.lbm_init(None, 1, 0.0) == native.LBM_EINVAL
+    assert lib.lbm_step_batch(None, 1) == native.LBM_EINVAL
+    assert lib.lbm_drag(None, 0, 1, None) == native.LBM_EINVAL
+    assert lib.lbm_destroy(None) == native.LBM_OK
+    assert lib.lbm_tile_count() >= 4

@@ -1,0 +1,212 @@
+"""GPU parity of the lattice-Boltzmann hot path against the FP64 oracle.
+
+Every test runs the HIP kernels through the C ABI and compares with the
+oracle on the same seeded inputs.  Tolerances:
+* drag series: max_t |f_gpu - f_orc| / max_t |f_orc| <= 1e-5 (FP32 storage and
+  arithmetic against FP64; relative per-sample error is undefined where the
+  drag crosses zero);
+* populations: the same max-norm relative error <= 1e-4 (FP32 round-off of
+  O(1e-7) per step, accumulated over up to 2000 steps of a weakly damped flow).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lbm as olbm
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _ensemble(members, cap):
+    from paper_2005_09323_amd.ensemble import Ensemble
+    return Ensemble(members, series_capacity=cap)
+
+
+def _channel(m):
+    return olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square)
+
+
+def _oracle(m, seed, member_index, amp, steps):
+    ch = _channel(m)
+    f0 = olbm.init_populations(ch, olbm.init_density(ch, seed, member_index, amp))
+    return olbm.run(ch, f0, steps)
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _state_err(ens, idx, m, fout):
+    ch = _channel(m)
+    fluid = ~olbm.solid_mask(ch)
+    gpu = ens.state(idx).double().cpu().numpy()
+    ref = fout - olbm.W[:, None, None]
+    return _rel(gpu[:, fluid], ref[:, fluid])
+
+
+def test_single_channel_2000_steps():
+    """256 x 64 channel, square 8, tau 0.55, g 1e-6, 2000 steps (the single-trajectory workload)."""
+    wl = workloads.single_channel()
+    m = wl.members[0]
+    ens = _ensemble([m], wl.steps)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(wl.steps - 1)
+    gpu = ens.drag(0, wl.steps).cpu().numpy()[0]
+    fout, ref = _oracle(m, wl.seed, 0, wl.noise_amp, wl.steps)
+    print("drag rel err", _rel(gpu, ref), "state rel err", _state_err(ens, 0, m, fout))
+    assert _rel(gpu, ref) <= 1e-5
+    assert _state_err(ens, 0, m, fout) <= 1e-4
+
+
+def test_ragged_mixed_shapes_all_tiles():
+    """Several shapes in one launch, sizes not multiples of any tile, every tile shape bit-identical."""
+    members = [workloads.Member(200, 37, 0.6, 2e-5, (50, 10, 6)),
+               workloads.Member(200, 37, 0.53, 1e-5, (120, 20, 5)),
+               workloads.Member(64, 16, 0.7, 4e-5, None),
+               workloads.Member(130, 21, 0.56, 3e-5, (1, 1, 3))]
+    steps = 300
+    from paper_2005_09323_amd import native
+    results = []
+    for tile in range(native.lib().lbm_tile_count()):
+        ens = _ensemble(members, steps)
+        ens.set_tile(tile)
+        ens.init(11, 1e-2)
+        ens.step(steps - 1)
+        torch.cuda.synchronize()
+        results.append((ens.drag(0, steps).cpu().numpy(), [ens.state(i).cpu().numpy().copy() for i in range(4)]))
+        ens.close()
+    drag0, states0 = results[0]
+    for i, m in enumerate(members):
+        fout, ref = _oracle(m, 11, i, 1e-2, steps)
+        fluid = ~olbm.solid_mask(_channel(m))
+        if m.square is not None:
+            assert _rel(drag0[i], ref) <= 1e-5, i
+        else:
+            assert np.all(drag0[i] == 0)
+        err = _rel(states0[i][:, fluid], (fout - olbm.W[:, None, None])[:, fluid])
+        assert err <= 1e-4, (i, err)
+    for drag, states in results[1:]:
+        assert np.array_equal(drag, drag0)
+        for i, m in enumerate(members):
+            fluid = ~olbm.solid_mask(_channel(m))
+            assert np.array_equal(states[i][:, fluid], states0[i][:, fluid])
+
+
+def test_rest_state_exact_and_deterministic():
+    m = workloads.Member(256, 64, 0.51, 0.0, (60, 28, 8))
+    ens = _ensemble([m, m], 50)
+    ens.init(1, 0.0)
+    ens.step(49)
+    fluid = torch.from_numpy(~olbm.solid_mask(_channel(m))).cuda()
+    for i in range(2):
+        assert torch.count_nonzero(ens.state(i)[:, fluid]) == 0
+    assert torch.count_nonzero(ens.drag(0, 50)) == 0
+
+
+def test_run_twice_bit_identical_and_mass_conserved():
+    m = workloads.Member(512, 128, 0.52, 2e-6, (120, 56, 16))
+    runs = []
+    for _ in range(2):
+        ens = _ensemble([m] * 3, 400)
+        ens.init(5, 1e-3)
+        fluid = torch.from_numpy(~olbm.solid_mask(_channel(m))).cuda()
+        mass0 = [ens.state(i)[:, fluid].double().sum().item() for i in range(3)]
+        ens.step(399)
+        mass1 = [ens.state(i)[:, fluid].double().sum().item() for i in range(3)]
+        runs.append((ens.drag(0, 400).cpu(), torch.stack([ens.state(i) for i in range(3)]).cpu()))
+        ens.close()
+        n_fluid = int(fluid.sum())
+        for a, b in zip(mass0, mass1):
+            assert abs(a - b) <= 1e-6 * n_fluid  # FP32 round-off of O(1e-8) per cell
+    assert torch.equal(runs[0][0], runs[1][0])
+    mask = ~olbm.solid_mask(_channel(m))
+    assert np.array_equal(runs[0][1].numpy()[:, :, mask], runs[1][1].numpy()[:, :, mask])
+
+
+def _golden(name):
+    return np.loadtxt(os.path.join(GOLDEN, name))
+
+
+@pytest.mark.parametrize("member,name", [(0, "ensemble1024_m0_drag1000.txt"),
+                                         (127, "ensemble1024_m127_drag1000.txt")])
+def test_full_ensemble_1024_against_stored_oracle(member, name):
+    """128 x 1024 x 256 (tau 0.5015, g 3e-6): the whole ensemble in one launch, members checked on 1000 steps."""
+    wl = workloads.ensemble_1024()
+    ens = _ensemble(wl.members, 1000)
+    ens.autotune(6)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(999)
+    gpu = ens.drag(0, 1000).cpu().numpy()
+    ref = _golden(name)
+    assert _rel(gpu[member], ref) <= 1e-5
+    ens.close()
+
+
+def test_mixed_sizes_against_stored_oracle():
+    wl = workloads.mixed_sizes()
+    ens = _ensemble(wl.members, 1000)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(999)
+    gpu = ens.drag(0, 1000).cpu().numpy()
+    for idx, name in ((0, "mixed_m0_drag1000.txt"), (64, "mixed_m64_drag1000.txt"),
+                      (191, "mixed_m191_drag1000.txt")):
+        assert _rel(gpu[idx], _golden(name)) <= 1e-5, idx
+    ens.close()
+
+
+def test_inactive_members_are_frozen_and_resume_exactly():
+    m = workloads.Member(128, 32, 0.6, 1e-5, (30, 12, 6))
+    ref = _ensemble([m, m], 120)
+    ref.init(3, 1e-3)
+    ref.step(100)
+    ens = _ensemble([m, m], 120)
+    ens.init(3, 1e-3)
+    ens.step(40)
+    ens.set_active([1, 0])
+    snap = ens.state(1).clone()
+    ens.step(60)
+    assert ens.time(0) == 101 and ens.time(1) == 41
+    assert torch.equal(ens.state(1), snap)
+    ens.set_active([0, 1])
+    ens.step(60)
+    ens.set_active(None)
+    fluid = torch.from_numpy(~olbm.solid_mask(_channel(m))).cuda()
+    for i in range(2):
+        assert torch.equal(ens.state(i)[:, fluid], ref.state(i)[:, fluid])
+    assert torch.equal(ens.drag(0, 101), ref.drag(0, 101))
+
+
+def test_nonfinite_member_is_flagged_and_isolated():
+    m = workloads.Member(128, 32, 0.6, 1e-5, (30, 12, 6))
+    ens = _ensemble([m] * 3, 60)
+    ens.init(2, 1e-3)
+    ens.state(1)[:, 14, 40] = float("nan")  # four cells from the square
+    ens.step(30)
+    flags = ens.flags().cpu().tolist()
+    assert flags == [0, 1, 0]
+    ref = _ensemble([m] * 3, 60)
+    ref.init(2, 1e-3)
+    ref.step(30)
+    assert torch.equal(ens.drag(0, 31)[0], ref.drag(0, 31)[0])
+    assert torch.equal(ens.drag(0, 31)[2], ref.drag(0, 31)[2])
+
+
+def test_capacity_and_argument_errors():
+    from paper_2005_09323_amd import native
+    m = workloads.Member(64, 16, 0.6, 1e-5, None)
+    ens = _ensemble([m], 10)
+    ens.init(1, 0.0)
+    ens.step(9)
+    with pytest.raises(native.LbmError) as e:
+        ens.step(1)
+    assert e.value.code == native.LBM_ERANGE
+    with pytest.raises(native.LbmError):
+        ens.set_tile(999)
+    ens.set_time(1)
+    ens.step(3)
+    assert ens.time() == 4
