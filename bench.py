@@ -57,6 +57,27 @@ def cpu_baseline(wl, steps: int):
                       f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
 
 
+def copy_calibration(mib: int, reps: int) -> None:
+    """Plain device-to-device copy of known size: reference for HBM byte counters and bandwidth."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                      "ms_per_copy": round(sec * 1e3, 4), "GBps_read_plus_write": round(8 * n / sec / 1e9, 1)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,7 +87,12 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="step-kernel tile id (-1: autotune)")
     ap.add_argument("--cpu-steps", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_traffic.json"))
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
+                    help="copy: time a plain device copy of --copy-mib MiB (counter calibration)")
+    ap.add_argument("--copy-mib", type=int, default=2048)
     args = ap.parse_args()
+    if args.mode == "copy":
+        return copy_calibration(args.copy_mib, max(args.steps, 1))
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build"}))
         sys.exit(2)

@@ -86,7 +86,8 @@ size_t lbm_state_floats(const lbm_member_desc* members, int32_t n_members);
 /*
  * Create a context for n_members trajectories.
  *   pop_a, pop_b   caller-owned device buffers of pop_floats floats each
- *                  (>= lbm_state_floats); states ping-pong between them.
+ *                  (>= lbm_state_floats), 16-byte aligned; states ping-pong
+ *                  between them.
  *   drag_series    caller-owned device float[n_members][series_capacity];
  *                  drag of step t goes to [m][t].
  *   accum          caller-owned device double[n_members]: running

@@ -11,7 +11,7 @@
 namespace lbm {
 
 constexpr int MAX_MEMBERS = 4096;
-constexpr int DEFAULT_TILE = 1;
+constexpr int DEFAULT_TILE = 0;
 
 struct MaskBits {
     unsigned w[MAX_MEMBERS / 32];
@@ -51,7 +51,6 @@ struct lbm_ctx {
     int chunk = 64;
     double mu = 0.0, sigma = 1.0, dt = 1.0;
     int tile_id = lbm::DEFAULT_TILE;
-    int xcd_remap = 1;
     int nseg = 0;
     int total_blocks = 0;
     lbm::Segment seg[lbm::MAX_SEGMENTS];

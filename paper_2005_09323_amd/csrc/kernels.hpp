@@ -13,7 +13,9 @@ struct Segment {
     int block_begin;       // first workgroup of the segment
     int member_begin;      // first member
     int tiles_per_member;  // tiles_x * tiles_y
-    int tiles_x;
+    int tiles_x;           // tiles of 256 columns
+    int vec;               // 1: width a multiple of 4, rows handled four cells per lane
+    int pad_;
 };
 
 struct StepArgs {
@@ -57,8 +59,9 @@ struct FinalizeArgs {
 };
 
 struct TileShape {
-    int tyt;  // thread rows per workgroup (workgroup = 64 x tyt threads)
-    int r;    // rows per thread
+    int tyt;  // waves per workgroup
+    int r;    // rows per wave (a tile is 256 columns by tyt * r rows)
+    int xcd;  // 1: remap workgroups so each XCD gets a contiguous range of tiles
 };
 
 extern const TileShape TILE_SHAPES[];

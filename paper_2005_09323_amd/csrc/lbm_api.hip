@@ -109,7 +109,7 @@ static int build_segments(lbm_ctx* c) {
         const auto& d = c->desc[m];
         const bool same = c->nseg > 0 && c->desc[c->seg[c->nseg - 1].member_begin].nx == d.nx &&
                           c->desc[c->seg[c->nseg - 1].member_begin].ny == d.ny;
-        const int tx = (d.nx + 63) / 64, ty = (d.ny + rows - 1) / rows;
+        const int tx = (d.nx + 255) / 256, ty = (d.ny + rows - 1) / rows;
         if (!same) {
             if (c->nseg == MAX_SEGMENTS)
                 return lbm_fail(LBM_EUNSUPPORTED, "more than %d runs of distinct lattice shapes; group members by shape",
@@ -119,6 +119,9 @@ static int build_segments(lbm_ctx* c) {
             s.member_begin = m;
             s.tiles_per_member = tx * ty;
             s.tiles_x = tx;
+            // four cells per lane needs 16-byte rows, and 32-bit byte offsets over the member's block
+            s.vec = (d.nx % 4 == 0 && 36LL * d.nx * d.ny < (1LL << 31)) ? 1 : 0;
+            s.pad_ = 0;
             c->seg[c->nseg++] = s;
         }
         if ((long long)blocks + (long long)tx * ty > (1LL << 31) - 1)
@@ -138,6 +141,7 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
     if (n_members > MAX_MEMBERS) return lbm_fail(LBM_EINVAL, "at most %d members", MAX_MEMBERS);
     if (!pop_a || !pop_b || !drag_series || !accum) return lbm_fail(LBM_EINVAL, "NULL device buffer");
     if (pop_a == pop_b) return lbm_fail(LBM_EINVAL, "pop_a and pop_b must be distinct buffers");
+    if (((uintptr_t)pop_a | (uintptr_t)pop_b) & 15) return lbm_fail(LBM_EINVAL, "population buffers must be 16-byte aligned");
     if (series_capacity < 1) return lbm_fail(LBM_EINVAL, "series_capacity must be >= 1");
     for (int i = 0; i < n_members; ++i) {
         int rc = validate_member(members[i], i);
@@ -317,7 +321,7 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
     a.pop0 = c->pop[0];
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
-    a.xcd = c->xcd_remap;
+    a.xcd = TILE_SHAPES[c->tile_id].xcd;
     a.total_blocks = c->total_blocks;
     a.nseg = c->nseg;
     for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
@@ -405,7 +409,6 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     a.pop0 = c->pop[0];
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
-    a.xcd = c->xcd_remap;
     // Steps are timed in pairs so every state ends in the buffer it started
     // in; the states do advance (untracked: no drag, no cursor), so callers
     // tune before lbm_init, which rebuilds step 0.
@@ -419,6 +422,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         c->tile_id = t;
         if (build_segments(c) != LBM_OK) continue;
         a.total_blocks = c->total_blocks;
+        a.xcd = TILE_SHAPES[t].xcd;
         a.nseg = c->nseg;
         for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
         a.slot = 0;

@@ -18,44 +18,54 @@ namespace lbm {
 // The populations are stored in FP32 but the update is computed in FP64:
 // the flow changes little from one step to the next, so FP32 rounding in
 // the update repeats with the same sign step after step and its error grows
-// linearly in time, while one rounding on store does not.
-__device__ __forceinline__ void bgk_guo(const MemberDev& m, const float din[9], double d[9]) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (double)din[i];
-    const double drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    const double jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
-    const double jy = ((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8]);
+// linearly in time, while one rounding on store does not.  The update is
+// done in place, one direction at a time, to keep few doubles live.
+//
+// links: bit i set when x + c_i lies in the square; returns the momentum
+// those links hand to the square, sum of 2 c_ix f_i^out (the w_i parts
+// cancel over the closed square, so deviations give the same total).
+__device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsigned links) {
+    const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+    const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
+    const double drho = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;
+    const double jx = ((d1 - d3) + (d5 - d6)) + (d8 - d7);
+    const double jy = ((d2 - d4) + (d5 - d7)) + (d6 - d8);
     const double rho = 1.0 + drho;
-    const double inv = 1.0 / rho;
+    // 1/rho: hardware FP32 reciprocal refined by two Newton steps in FP64
+    // (relative error ~1e-14 << the FP32 storage rounding)
+    double inv = (double)__builtin_amdgcn_rcpf((float)rho);
+    inv = inv * (2.0 - rho * inv);
+    inv = inv * (2.0 - rho * inv);
     const double ux = (jx + m.half_fx) * inv;
     const double uy = jy * inv;
     const double usq = 1.5 * (ux * ux + uy * uy);
     const double om = m.omega;
+    double drag = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
+        const double di = (double)d[i];
         const double cu = (double)CX[i] * ux + (double)CY[i] * uy;
         const double deq = WD[i] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq));
         const double src = WD[i] * (m.gf3 * ((double)CX[i] - ux) + m.gf9 * cu * (double)CX[i]);
-        d[i] = d[i] + om * (deq - d[i]) + src;
+        const double out = di + om * (deq - di) + src;
+        if (CX[i] != 0 && (links >> i) & 1u) drag += 2.0 * (double)CX[i] * out;
+        d[i] = (float)out;
     }
+    return drag;
 }
 
-// Momentum handed to the square by one ring cell: sum over its links into
-// the square of 2 c_ix f_i^out (the w_i parts cancel over the closed square,
-// so deviations give the same total).
-__device__ __forceinline__ double ring_drag(const MemberDev& m, const double d[9], int x, int y) {
-    double acc = 0.0;
+// Directions of (x, y) whose next cell lies in the square (x-moving ones only).
+__device__ __forceinline__ unsigned square_links(const MemberDev& m, int x, int y) {
+    unsigned mask = 0;
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        if (CX[i] == 0) continue;
-        if (in_square(m, x + CX[i], y + CY[i])) acc += 2.0 * (double)CX[i] * d[i];
-    }
-    return acc;
+    for (int i = 1; i < 9; ++i)
+        if (CX[i] != 0 && in_square(m, x + CX[i], y + CY[i])) mask |= 1u << i;
+    return mask;
 }
 
 // Workgroup -> (member, tile): members are grouped in segments of equal
 // lattice shape; within a segment tiles run x-fastest, then y, then member.
-__device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx, int& ty) {
+__device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx, int& ty, int& vec) {
     int s = 0;
 #pragma unroll 1
     while (s + 1 < a.nseg && b >= a.seg[s + 1].block_begin) ++s;
@@ -64,6 +74,7 @@ __device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx
     const int tile = local - mloc * a.seg[s].tiles_per_member;
     ty = tile / a.seg[s].tiles_x;
     tx = tile - ty * a.seg[s].tiles_x;
+    vec = a.seg[s].vec;
     return a.seg[s].member_begin + mloc;
 }
 
@@ -77,44 +88,178 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
     return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
 }
 
+// One fluid-or-solid cell, one population per lane access: used for lattices
+// whose width is not a multiple of 4.
+__device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
+                                            double* __restrict__ part, int x, int y) {
+    const int nx = m.nx, ny = m.ny;
+    const long long plane = (long long)nx * ny;
+    if (in_square(m, x, y)) return;
+    float dl[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int xs = x - CX[i];
+        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+        const int ys = y - CY[i];
+        const bool bounce = (ys < 0) | (ys >= ny) | in_square(m, xs, ys);
+        const long long idx = bounce ? (long long)OPP[i] * plane + (long long)y * nx + x
+                                     : (long long)i * plane + (long long)ys * nx + xs;
+        dl[i] = src[idx];
+    }
+    const int ri = ring_index(m, x, y);
+    const double drag = bgk_guo(m, dl, ri >= 0 ? square_links(m, x, y) : 0u);
+    const long long cell = (long long)y * nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = dl[i];
+    if (ri >= 0) part[ri] = drag;
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Word 3 of a raw (untyped) buffer resource on the GFX9/CDNA family, and the
+// cache-policy bit that marks a store non-temporal on gfx94x/gfx950.
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
+constexpr int BUFFER_NT = 2;
+
+// DPP wave shifts (GFX9 data-parallel primitives): lane l receives the value
+// of lane l-1 (shr) or l+1 (shl); the lane without a source is replaced by
+// the caller.
+__device__ __forceinline__ float wave_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_shl1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// One row segment of up to 256 cells per wave, four consecutive cells per
+// lane, 16-byte loads and stores.  A population moving along +x (c_x = 1) is
+// pulled from x - 1: the lane's aligned float4 supplies three of its four
+// cells and the fourth comes from the neighbouring lane through a wave
+// shift; the first lane of the wave takes it from one wave-uniform load,
+// which also carries the periodic wrap at x = 0.  Likewise for c_x = -1 at
+// the right end.  Rows next to a wall are wave-uniform (the whole row
+// bounces back); only waves touching the square decide per cell.
+__device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
+                                        double* __restrict__ part, int base, int y, int lane) {
+    const int nx = m.nx, ny = m.ny;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const int nvalid = min(256, nx - base);  // a multiple of 4
+    const int last = nvalid / 4 - 1;         // last lane holding cells
+    const bool live = lane <= last;
+    const int x0 = base + 4 * min(lane, last);
+    const unsigned voff = 4u * (unsigned)x0;  // per-lane byte offset within a row
+    const unsigned rowoff = (unsigned)y * (unsigned)nx;
+    const int xl = (base == 0 ? nx : base) - 1;
+    const int xr = (base + nvalid == nx) ? 0 : base + nvalid;
+    const bool near_sq = m.ss > 0 && y >= m.sy0 - 1 && y <= m.sy0 + m.ss && base <= m.sx0 + m.ss &&
+                         base + nvalid - 1 >= m.sx0 - 1;
+    // buffer resources over the member's whole block (range-checked by the hardware);
+    // row offsets are wave-uniform (scalar), the lane offset is the only vector operand
+    const unsigned bytes = 36u * plane;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, (int)bytes, BUFFER_RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc((void*)dst, (short)0, (int)bytes, BUFFER_RSRC_WORD3);
+    // load phase: nine 16-byte loads and the edge elements, no branches in
+    // between (row choice by wave-uniform selects), so all are in flight at once
+    f4 v[9];
+    float e[9];
+    bool wall[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int ys = y - CY[i];
+        wall[i] = ys < 0 || ys >= ny;  // the whole row takes its own opposite population
+        const unsigned row = wall[i] ? (unsigned)OPP[i] * plane + rowoff : (unsigned)i * plane + (unsigned)ys * (unsigned)nx;
+        v[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * row, 0);
+        // the edge element goes through the vector memory pipe like the rest
+        // (every lane asks for the same word)
+        e[i] = CX[i] == 1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0))
+                          : (CX[i] == -1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0)) : 0.0f);
+    }
+    // shift phase: +x movers take x - 1 from the left neighbour lane, -x movers x + 1 from the right
+    f4 p[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (CX[i] == 1) {
+            const float sh = wave_shr1(v[i].w);
+            const f4 s4 = f4{lane == 0 ? e[i] : sh, v[i].x, v[i].y, v[i].z};
+            p[i] = wall[i] ? v[i] : s4;
+        } else if (CX[i] == -1) {
+            const float sh = wave_shl1(v[i].x);
+            const f4 s4 = f4{v[i].y, v[i].z, v[i].w, lane == last ? e[i] : sh};
+            p[i] = wall[i] ? v[i] : s4;
+        } else {
+            p[i] = v[i];
+        }
+    }
+    if (near_sq) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int ys = y - CY[i];
+            if (ys < 0 || ys >= ny) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (in_square(m, x0 + k - CX[i], ys)) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+        }
+    }
+    // collide the four cells one after the other, in place
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        float dl[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) dl[i] = p[i][k];
+        const int ri = (near_sq && live && !in_square(m, x0 + k, y)) ? ring_index(m, x0 + k, y) : -1;
+        const double drag = bgk_guo(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) p[i][k] = dl[i];
+        if (ri >= 0) part[ri] = drag;
+    }
+    if (!live) return;
+    if (!near_sq) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            __builtin_amdgcn_raw_buffer_store_b128(p[i], rd, voff, 4u * ((unsigned)i * plane + rowoff), BUFFER_NT);
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            if (in_square(m, x0 + k, y)) continue;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[(unsigned)i * plane + rowoff + (unsigned)(x0 + k)] = p[i][k];
+        }
+    }
+}
+
+// Fused pull-stream + collide step over the whole ensemble.  Workgroup =
+// TYT waves; a tile is 256 columns by TYT*R rows; wave w handles rows
+// w, w + TYT, ... of the tile.
 template <int TYT, int R>
 __global__ __launch_bounds__(64 * TYT) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
-    int tx, ty;
-    const int mi = block_to_member(a, b, tx, ty);
-    if (!a.active[mi]) return;
+    int tx, ty, vec;
+    const int mi = block_to_member(a, b, tx, ty, vec);
+    // the three bookkeeping reads are independent: issue them together
+    const int on = a.active[mi];
     const MemberDev m = a.members[mi];
     const int par = a.parity[mi] ^ a.flip;
+    if (!on) return;
     const float* __restrict__ src = (par ? a.pop1 : a.pop0) + m.off;
     float* __restrict__ dst = (par ? a.pop0 : a.pop1) + m.off;
-    const int nx = m.nx, ny = m.ny;
-    const long long plane = (long long)nx * ny;
-    const int x = tx * 64 + (int)(threadIdx.x & 63);
-    const int ly = (int)(threadIdx.x >> 6);
-    if (x >= nx) return;
+    double* __restrict__ part = a.partial + m.part_off + (long long)a.slot * m.ring;
+    const int lane = (int)(threadIdx.x & 63);
+    // the wave index is uniform across the wave: say so, so that all row logic stays scalar
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int base = tx * 256;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int y = ty * (TYT * R) + r * TYT + ly;
-        if (y >= ny) break;
-        if (in_square(m, x, y)) continue;
-        float dl[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            int xs = x - CX[i];
-            xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-            const int ys = y - CY[i];
-            const bool bounce = (ys < 0) | (ys >= ny) | in_square(m, xs, ys);
-            const long long idx = bounce ? (long long)OPP[i] * plane + (long long)y * nx + x
-                                         : (long long)i * plane + (long long)ys * nx + xs;
-            dl[i] = src[idx];
+        const int y = ty * (TYT * R) + r * TYT + wv;
+        if (y >= m.ny) break;
+        if (vec) {
+            vec_row(m, src, dst, part, base, y, lane);
+        } else {
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                const int x = base + 64 * k + lane;
+                if (x < m.nx) scalar_cell(m, src, dst, part, x, y);
+            }
         }
-        double d[9];
-        bgk_guo(m, dl, d);
-        const long long cell = (long long)y * nx + x;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = (float)d[i];
-        const int ri = ring_index(m, x, y);
-        if (ri >= 0) a.partial[m.part_off + (long long)a.slot * m.ring + ri] = ring_drag(m, d, x, y);
     }
 }
 
@@ -132,16 +277,15 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         const U64x4 w = philox4x64_10((uint64_t)cell, (uint64_t)mi, 0, 0, a.seed, PURPOSE_INIT);
         drho = a.noise_amp * (2.0 * uniform53(w.v[0]) - 1.0);
     }
-    float d0[9];
+    float d[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d0[i] = (float)(WD[i] * drho);
-    double d[9];
-    bgk_guo(m, d0, d);
+    for (int i = 0; i < 9; ++i) d[i] = (float)(WD[i] * drho);
+    const int ri = ring_index(m, x, y);
+    const double drag = bgk_guo(m, d, ri >= 0 ? square_links(m, x, y) : 0u);
     float* dst = a.pop0 + m.off;  // step 0 lives in buffer 0 (parity 0)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = (float)d[i];
-    const int ri = ring_index(m, x, y);
-    if (ri >= 0) a.partial[m.part_off + ri] = ring_drag(m, d, x, y);
+    for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = d[i];
+    if (ri >= 0) a.partial[m.part_off + ri] = drag;
 }
 
 // Reduce the drag partials of a chunk of n steps for one member per block:
@@ -191,22 +335,24 @@ static hipError_t launch_step_t(const StepArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Table of step-kernel tile shapes: threads 64 x TYT, each thread R rows.
+// Table of step-kernel launch shapes: TYT waves per workgroup, R rows per
+// wave, and whether workgroups are remapped so each XCD gets contiguous tiles.
 const TileShape TILE_SHAPES[] = {
-    {4, 1}, {4, 2}, {4, 4}, {2, 4}, {8, 1}, {8, 2}, {16, 1}, {1, 8},
+    {4, 1, 1}, {4, 2, 1}, {8, 1, 1}, {2, 2, 1}, {16, 1, 1}, {1, 4, 1}, {4, 4, 1}, {8, 2, 1},
+    {4, 1, 0}, {4, 2, 0}, {8, 1, 0}, {2, 2, 0}, {16, 1, 0}, {1, 4, 0}, {4, 4, 0}, {8, 2, 0},
 };
 const int N_TILE_SHAPES = (int)(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
 
 hipError_t launch_step(int tile_id, const StepArgs& a, hipStream_t st) {
-    switch (tile_id) {
+    switch (tile_id % 8) {
         case 0: return launch_step_t<4, 1>(a, st);
         case 1: return launch_step_t<4, 2>(a, st);
-        case 2: return launch_step_t<4, 4>(a, st);
-        case 3: return launch_step_t<2, 4>(a, st);
-        case 4: return launch_step_t<8, 1>(a, st);
-        case 5: return launch_step_t<8, 2>(a, st);
-        case 6: return launch_step_t<16, 1>(a, st);
-        case 7: return launch_step_t<1, 8>(a, st);
+        case 2: return launch_step_t<8, 1>(a, st);
+        case 3: return launch_step_t<2, 2>(a, st);
+        case 4: return launch_step_t<16, 1>(a, st);
+        case 5: return launch_step_t<1, 4>(a, st);
+        case 6: return launch_step_t<4, 4>(a, st);
+        case 7: return launch_step_t<8, 2>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

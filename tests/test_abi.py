@@ -26,7 +26,7 @@ def test_state_floats():
     assert lib.lbm_state_floats(None, 0) == 0
 
 
-def _create(members, pop_floats=10**9, cap=10, a=1, b=2, series=3, accum=4):
+def _create(members, pop_floats=10**9, cap=10, a=256, b=512, series=768, accum=1024):
     lib = native.lib()
     ctx = ctypes.c_void_p()
     arr = native.desc_array(members)
@@ -51,7 +51,9 @@ def test_create_rejects_bad_buffers():
     m = workloads.Member(64, 16, 0.6, 0.0, (10, 4, 4))
     assert _create([m], pop_floats=9 * 64 * 16 - 1)[0] == native.LBM_EINVAL
     assert _create([m], a=0)[0] == native.LBM_EINVAL
-    assert _create([m], a=5, b=5)[0] == native.LBM_EINVAL
+    assert _create([m], a=256, b=256)[0] == native.LBM_EINVAL
+    rc, err = _create([m], a=260)
+    assert rc == native.LBM_EINVAL and "aligned" in err
     assert _create([m], cap=0)[0] == native.LBM_EINVAL
     assert _create([])[0] == native.LBM_EINVAL
 
