@@ -177,7 +177,9 @@ int lbm_autotune(lbm_ctx* ctx, int32_t n_steps, int32_t* best_tile);
  *   snapshots: device, n_snap states in this library's deviation layout
  *   ([n_snap][9][ny][nx]); may be NULL when eps == 0 or n_snap == 0.
  *   accum is reset to 0; flags are copied from the ancestor.
- * LBM_ENONFINITE if every s_n is non-finite (nothing is changed).
+ * LBM_ENONFINITE if every s_n is non-finite (nothing is changed).  Waits once
+ * on the context's stream (after the selection, to read its status).
+ * Members <= 4096.
  */
 int gktl_select_clone(lbm_ctx* ctx, double k, uint64_t key, int32_t period,
                       double eps, const float* snapshots, int32_t n_snap,
@@ -213,7 +215,7 @@ int lbm_copy_state_in(lbm_ctx* ctx, int32_t m, const float* src_dev, int32_t t);
  * word 0, into parent_dev[j]; branch_t_dev[j] is the first column where the
  * parent's score is strictly above the level.  n_killed_dev (device int32)
  * receives K, level_dev (device float) the level.  If every member is at the
- * level (extinction) K = N and parents/branch times are -1.
+ * level (extinction) K = N and parents/branch times are -1.  N <= 2048.
  */
 int ams_score_kill_branch(const float* series_dev, int32_t n, int32_t t_len, int32_t n_kill,
                           uint64_t key, int32_t iteration,

@@ -130,6 +130,17 @@ def reconstruct_series(period_series: List[np.ndarray], ancestors: List[np.ndarr
     return np.concatenate(segs, axis=1)
 
 
+def window_means(series: np.ndarray, window: int) -> np.ndarray:
+    """[N, T] -> [N, T]: mean of the last `window` samples ending at t (-inf before the first full window)."""
+    series = np.asarray(series, dtype=np.float64)
+    n, t_len = series.shape
+    out = np.full((n, t_len), -math.inf)
+    for j in range(n):
+        for t in range(window - 1, t_len):
+            out[j, t] = math.fsum(series[j, t - window + 1:t + 1].tolist()) / window
+    return out
+
+
 def window_mean_max(series: np.ndarray, window: int) -> np.ndarray:
     """max over t of the window mean (1/T) sum of the last T samples; one per row."""
     series = np.asarray(series, dtype=np.float64)

@@ -24,6 +24,15 @@ hipError_t set_bits(int* p, int n, const MaskBits& bits, hipStream_t st);
 
 }  // namespace lbm
 
+struct RareScratch {
+    bool ready = false;
+    int blocks_per_state = 0;
+    double *prefix = nullptr, *alpha = nullptr, *alpha_sum = nullptr, *scale = nullptr, *coef_w = nullptr;
+    double* mass_partial = nullptr;
+    int *mode = nullptr, *src = nullptr, *need_mass = nullptr, *flags_new = nullptr, *status = nullptr;
+    int* status_host = nullptr;
+};
+
 struct lbm_ctx {
     int n = 0;
     std::vector<lbm_member_desc> desc;
@@ -54,7 +63,10 @@ struct lbm_ctx {
     int nseg = 0;
     int total_blocks = 0;
     lbm::Segment seg[lbm::MAX_SEGMENTS];
+    RareScratch rare;
 };
+
+void free_rare_scratch(lbm_ctx* c);
 
 int lbm_fail(int code, const char* fmt, ...);
 int lbm_hip_fail(hipError_t e, const char* what);

@@ -235,6 +235,7 @@ extern "C" int lbm_destroy(lbm_ctx* c) {
     hipFree(c->d_partial);
     hipFree(c->d_scratch);
     hipFree(c->d_iscratch);
+    free_rare_scratch(c);
     delete c;
     return LBM_OK;
 }

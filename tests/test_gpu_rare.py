@@ -1,0 +1,258 @@
+"""GPU parity of GKTL cloning, branching perturbation and AMS selection.
+
+Selections are compared with the oracle exactly (indices, levels, branch
+times): both sides take every decision in FP64 (GKTL) or on the same FP32
+scores (AMS), with independent Philox implementations.  Perturbed states are
+compared elementwise, relative to the largest deviation: <= 1e-6 (one FP32
+rounding of values formed in FP64).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import ams as oams
+from oracle import gktl as ogktl
+from oracle import lbm as olbm
+from oracle import ou as oou
+from oracle import perturb as opert
+
+pytestmark = pytest.mark.gpu
+
+
+def _ens(members, cap=64):
+    from paper_2005_09323_amd.ensemble import Ensemble
+    return Ensemble(members, series_capacity=cap)
+
+
+def _channel(m):
+    return olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square)
+
+
+def _oracle_state(m, seed, steps):
+    """Post-collision populations of an oracle run (FP64) and the same as FP32 deviations."""
+    ch = _channel(m)
+    f, _ = olbm.run(ch, olbm.init_populations(ch, olbm.init_density(ch, seed, 0, 1e-2)), steps)
+    dev32 = (f - olbm.W[:, None, None]).astype(np.float32)
+    dev32[:, olbm.solid_mask(ch)] = 0.0
+    return dev32
+
+
+def _full(dev32, ch):
+    """FP64 full populations of FP32 deviations (solid cells zero)."""
+    f = dev32.astype(np.float64) + olbm.W[:, None, None]
+    f[:, olbm.solid_mask(ch)] = 0.0
+    return f
+
+
+@pytest.mark.parametrize("n,n_bad,k,seed", [(64, 0, 1.5, 1), (64, 7, 0.3, 2), (256, 3, 4.0, 3), (1000, 0, 1.0, 4)])
+def test_gktl_selection_matches_oracle(n, n_bad, k, seed):
+    m = workloads.Member(8, 4, 0.6, 0.0, None)
+    ens = _ens([m] * n)
+    ens.init(0, 0.0)
+    s = workloads.log_weights(n, seed, scale=2.0, n_bad=n_bad)
+    for period in range(3):
+        ens.accum.copy_(torch.from_numpy(s / k))
+        anc, lnr = ens.gktl_select_clone(k, key=77 + seed, period=period)
+        accum_used = s / k
+        ref = ogktl.select(k * accum_used, 77 + seed, period)
+        assert np.array_equal(anc.cpu().numpy(), ref)
+        assert math.isclose(lnr.item(), ogktl.log_normaliser(k * accum_used), rel_tol=1e-13, abs_tol=1e-13)
+        assert torch.count_nonzero(ens.accum) == 0
+
+
+def test_gktl_all_nonfinite_is_rejected_and_changes_nothing():
+    from paper_2005_09323_amd import native
+    m = workloads.Member(16, 8, 0.6, 1e-5, None)
+    ens = _ens([m] * 4)
+    ens.init(1, 1e-3)
+    before = [ens.state(i).clone() for i in range(4)]
+    ens.accum.fill_(float("nan"))
+    with pytest.raises(native.LbmError) as e:
+        ens.gktl_select_clone(1.0, 1, 0)
+    assert e.value.code == native.LBM_ENONFINITE
+    for i in range(4):
+        assert torch.equal(ens.state(i), before[i])
+
+
+def test_gktl_clone_copies_ancestor_states_exactly():
+    m = workloads.Member(64, 16, 0.6, 2e-5, (20, 5, 4))
+    n = 12
+    ens = _ens([m] * n)
+    ens.init(5, 1e-3)
+    ens.step(7)
+    fluid = torch.from_numpy(~olbm.solid_mask(_channel(m))).cuda()
+    before = [ens.state(i)[:, fluid].clone() for i in range(n)]
+    ens.accum.copy_(torch.from_numpy(workloads.log_weights(n, 9, scale=3.0)))
+    anc, _ = ens.gktl_select_clone(1.0, key=3, period=1)
+    anc = anc.cpu().tolist()
+    assert len(set(anc)) < n  # some trajectory was cloned, some killed
+    for i in range(n):
+        assert torch.equal(ens.state(i)[:, fluid], before[anc[i]])
+    ens.step(5)  # the ensemble keeps running from the new states
+    assert ens.time() == 13
+
+
+def test_gktl_perturbation_and_mass_rescale_match_oracle():
+    m = workloads.Member(64, 16, 0.56, 2e-5, (20, 5, 4))
+    ch = _channel(m)
+    fluid = ~olbm.solid_mask(ch)
+    n, n_snap, eps, key, period = 6, 10, 0.002, 21, 4
+    states = [_oracle_state(m, 100 + i, 3 + i) for i in range(n)]
+    snaps = np.stack([_oracle_state(m, 200 + q, 5) for q in range(n_snap)])
+    ens = _ens([m] * n)
+    ens.init(0, 0.0)
+    for i in range(n):
+        ens.copy_state_in(i, torch.from_numpy(states[i]).cuda(), 1)
+    # member 2 dominates, so it is copied several times
+    s = np.array([-2.0, 0.1, 3.0, -1.0, 0.5, -0.3])
+    ens.accum.copy_(torch.from_numpy(s))
+    anc, _ = ens.gktl_select_clone(1.0, key=key, period=period, eps=eps,
+                                   snapshots=torch.from_numpy(snaps).cuda())
+    anc = anc.cpu().numpy()
+    ref_anc = ogktl.select(s, key, period)
+    assert np.array_equal(anc, ref_anc)
+    first = ogktl.first_copy(anc)
+    assert not first.all()
+    snaps_full = np.stack([_full(snaps[q], ch) for q in range(n_snap)])
+    for i in range(n):
+        gpu = ens.state(i).double().cpu().numpy()
+        parent = _full(states[anc[i]], ch)
+        if first[i]:
+            assert np.array_equal(gpu[:, fluid], states[anc[i]][:, fluid].astype(np.float64))
+            continue
+        expect = opert.perturb(parent, snaps_full, opert.alphas(key, i, period, n_snap), eps, fluid)
+        ref = (expect - olbm.W[:, None, None])[:, fluid]
+        err = np.abs(gpu[:, fluid] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-6, (i, err)
+        m_gpu = math.fsum((gpu[:, fluid] + olbm.W[:, None]).ravel())
+        assert abs(m_gpu / opert.total_mass(parent, fluid) - 1) < 2e-7
+
+
+def test_in_place_perturbation_matches_oracle():
+    m = workloads.Member(64, 16, 0.56, 2e-5, (20, 5, 4))
+    ch = _channel(m)
+    fluid = ~olbm.solid_mask(ch)
+    n, n_snap, eps, key, period = 4, 3, 0.01, 8, 11
+    states = [_oracle_state(m, 300 + i, 2) for i in range(n)]
+    snaps = np.stack([_oracle_state(m, 400 + q, 4) for q in range(n_snap)])
+    ens = _ens([m] * n)
+    ens.init(0, 0.0)
+    for i in range(n):
+        ens.copy_state_in(i, torch.from_numpy(states[i]).cuda(), 1)
+    ens.perturb([0, 1, 0, 1], key, period, eps, torch.from_numpy(snaps).cuda())
+    snaps_full = np.stack([_full(snaps[q], ch) for q in range(n_snap)])
+    for i in range(n):
+        gpu = ens.state(i).double().cpu().numpy()[:, fluid]
+        if i in (0, 2):
+            assert np.array_equal(gpu, states[i][:, fluid].astype(np.float64))
+        else:
+            exp = opert.perturb(_full(states[i], ch), snaps_full, opert.alphas(key, i, period, n_snap), eps, fluid)
+            ref = (exp - olbm.W[:, None, None])[:, fluid]
+            assert np.abs(gpu - ref).max() / np.abs(ref).max() <= 1e-6
+
+
+def test_gktl_full_ensemble_1024_gather_and_perturb():
+    """256 clones of 1024 x 256: selection exact, copies exact, perturbed clones keep mass and
+    are one scalar times (parent + eps sum alpha_n snapshot_n) at every sampled cell."""
+    wl = workloads.gktl_ensemble()
+    m = wl.members[0]
+    ch = _channel(m)
+    fluid_np = ~olbm.solid_mask(ch)
+    fluid = torch.from_numpy(fluid_np).cuda()
+    n = len(wl.members)
+    eps, n_snap, key, period = 0.002, 10, 5, 2
+    snaps = workloads.snapshot_states(n_snap, m, 500)
+    snaps_t = torch.from_numpy(snaps).cuda()
+    ens = _ens(wl.members, 300)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(20)
+    before = torch.stack([ens.state(i) for i in range(n)]).clone()
+    s = workloads.log_weights(n, 31, scale=1.5)
+    ens.accum.copy_(torch.from_numpy(s))
+    anc, _ = ens.gktl_select_clone(1.0, key=key, period=period, eps=eps, snapshots=snaps_t)
+    anc = anc.cpu().numpy()
+    assert np.array_equal(anc, ogktl.select(s, key, period))
+    first = ogktl.first_copy(anc)
+    rng = np.random.default_rng(0)
+    cells = np.flatnonzero(fluid_np.ravel())[rng.integers(0, int(fluid_np.sum()), 2000)]
+    snaps_full = torch.from_numpy(np.stack([_full(snaps[q], ch) for q in range(n_snap)])).cuda()
+    w = torch.from_numpy(olbm.W).cuda()
+    for i in range(n):
+        new = ens.state(i)
+        par = before[anc[i]]
+        if first[i]:
+            assert torch.equal(new[:, fluid], par[:, fluid])
+            continue
+        if i % 16:
+            continue  # check a sample of the perturbed members
+        al = torch.from_numpy(opert.alphas(key, i, period, n_snap)).cuda()
+        f_par = par.double() + w[:, None, None]
+        shifted = f_par + eps * torch.einsum("q,qiyx->iyx", al, snaps_full)
+        f_new = new.double() + w[:, None, None]
+        ratio = (f_new.reshape(9, -1)[:, cells] / shifted.reshape(9, -1)[:, cells])
+        assert (ratio.max() - ratio.min()).item() < 1e-6
+        m_new = f_new[:, fluid].sum().item()
+        m_par = f_par[:, fluid].sum().item()
+        assert abs(m_new / m_par - 1) < 1e-7
+    ens.close()
+
+
+def test_gktl_on_ou_with_device_selection():
+    """The device selection drives a GKTL run of the OU process; the SCGF matches its closed form."""
+    dt, steps, n_per, n, k = 0.05, 10, 10, 512, 1.0
+    t_a = dt * steps * n_per
+    exact = oou.log_mgf_sum(k, steps * n_per, dt) / t_a
+    carrier = workloads.Member(8, 4, 0.6, 0.0, None)
+    est = []
+    for rep in range(4):
+        ens = _ens([carrier] * n)
+        ens.init(0, 0.0)
+        rng = np.random.default_rng(900 + rep)
+        x = oou.stationary(n, rng)
+        ln_r = []
+        for i in range(n_per):
+            path = oou.paths(x, steps, dt, rng)
+            ens.accum.copy_(torch.from_numpy(path.sum(axis=1) * dt))
+            anc, lnr = ens.gktl_select_clone(k, key=rep, period=i)
+            ln_r.append(lnr.item())
+            x = path[anc.cpu().numpy(), -1]
+        est.append(ogktl.scgf(ln_r, t_a))
+        ens.close()
+    mean, se = np.mean(est), np.std(est, ddof=1) / math.sqrt(len(est))
+    assert abs(mean - exact) < 4 * se + 0.03 * exact, (mean, exact)
+
+
+@pytest.mark.parametrize("n,t_len,n_kill,seed", [(32, 100, 1, 0), (512, 300, 26, 1), (2048, 64, 200, 2)])
+def test_ams_selection_matches_oracle(n, t_len, n_kill, seed):
+    from paper_2005_09323_amd.ensemble import ams_score_kill_branch
+    series = workloads.score_series(n, t_len, seed)
+    series[3, 10] = np.nan                       # a blown-up member
+    series[5] = series[6]                        # a tie
+    for it in range(3):
+        res = ams_score_kill_branch(torch.from_numpy(series).cuda(), n_kill, key=40 + seed, iteration=it)
+        ref = oams.kill_branch(series.astype(np.float64), n_kill, 40 + seed, it)
+        assert res["level"] == ref.level
+        assert np.array_equal(res["killed"].cpu().numpy(), ref.killed)
+        assert np.array_equal(res["parents"].cpu().numpy(), ref.parents)
+        assert np.array_equal(res["branch_t"].cpu().numpy(), ref.branch_t)
+        assert np.array_equal(res["maxima"].cpu().numpy().astype(np.float64), oams.clean_maxima(series))
+
+
+def test_ams_extinction():
+    from paper_2005_09323_amd.ensemble import ams_score_kill_branch
+    series = np.ones((8, 5), dtype=np.float32)
+    res = ams_score_kill_branch(torch.from_numpy(series).cuda(), 2, key=1, iteration=0)
+    assert res["n_killed"] == 8
+    assert np.all(res["parents"].cpu().numpy() == -1)
+
+
+def test_window_mean_score_matches_oracle():
+    from paper_2005_09323_amd.ensemble import window_mean
+    series = workloads.score_series(5, 400, 7)
+    gpu = window_mean(torch.from_numpy(series).cuda(), 64).cpu().numpy()
+    ref = ogktl.window_means(series.astype(np.float64), 64)
+    assert np.all(np.isneginf(gpu[:, :63]))
+    assert np.allclose(gpu[:, 63:], ref[:, 63:], rtol=2e-7, atol=1e-7)

@@ -158,3 +158,12 @@ def test_return_time_poisson_limits():
     assert math.isclose(r[1] * p[1] / 6.0, 1.0, rel_tol=1e-8)
     assert math.isclose(r[3], 6.0 / math.log(2.0), rel_tol=1e-14)
     assert np.all(np.diff(r[1:]) < 0)
+
+
+def test_window_means_consistent_with_max():
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((2, 30))
+    wm = gktl.window_means(x, 7)
+    assert np.all(np.isneginf(wm[:, :6]))
+    assert np.allclose(wm[:, 6:].max(axis=1), gktl.window_mean_max(x, 7), rtol=1e-15)
+    assert np.isclose(wm[1, 12], x[1, 6:13].mean(), rtol=1e-14)

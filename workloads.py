@@ -143,3 +143,25 @@ def cnn_batch(batch: int, seed: int, c_in: int = 3, hw: int = 16):
     """Random feature batch [B, c_in, hw, hw] and labels [B]."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((batch, c_in, hw, hw)), rng.standard_normal(batch)
+
+
+def snapshot_states(n_snap: int, member: Member, seed: int) -> np.ndarray:
+    """Arbitrary flow-like snapshots as FP32 deviations [n_snap, 9, ny, nx] (zero in the square):
+    d_i = w_i * 1e-3 * (density + 3 c_i.u) with smooth random fields."""
+    rng = np.random.default_rng(seed)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    out = np.empty((n_snap, 9, member.ny, member.nx), dtype=np.float32)
+    yy, xx = np.meshgrid(np.arange(member.ny), np.arange(member.nx), indexing="ij")
+    for q in range(n_snap):
+        k1, k2, ph = rng.integers(1, 5), rng.integers(1, 5), rng.uniform(0, 2 * np.pi, 3)
+        rho = np.sin(2 * np.pi * k1 * xx / member.nx + ph[0]) * np.cos(np.pi * k2 * yy / member.ny + ph[1])
+        ux = np.cos(2 * np.pi * k2 * xx / member.nx + ph[2])
+        uy = 0.3 * rho
+        for i in range(9):
+            out[q, i] = (w[i] * 1e-3 * (rho + 3 * (cx[i] * ux + cy[i] * uy))).astype(np.float32)
+        if member.square is not None:
+            x0, y0, s = member.square
+            out[q, :, y0:y0 + s, x0:x0 + s] = 0.0
+    return out
