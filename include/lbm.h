@@ -232,6 +232,50 @@ int ams_score_kill_branch(const float* series_dev, int32_t n, int32_t t_len, int
 int lbm_window_mean(const float* series_dev, int32_t n, int32_t ld, int32_t t_len, int32_t window,
                     float* out_dev, void* hip_stream);
 
+/*
+ * Learned AMS score (the paper's conclusion proposes learning the score
+ * function).  A small network maps a 3 x 16 x 16 picture of the near wake to
+ * one number: three zero-padded 3x3 convolutions with 32 output channels and
+ * ReLU, a global average over the 16 x 16 positions and a linear read-out.
+ * Parameters are one FP32 vector (score_net_params() floats) in the order
+ * w1[32][3][3][3], b1[32], w2[32][32][3][3], b2[32], w3[32][32][3][3], b3[32],
+ * w4[32], b4; convolution weights [out][in][dy][dx] act as cross-correlation.
+ * The convolutions run on BF16 matrix cores: weights and layer inputs are
+ * rounded to BF16 (nearest even), sums are FP32.
+ */
+int32_t score_net_params(void);
+
+/* Device workspace (256-byte aligned) score_net_forward / score_net_grad need for a batch. */
+size_t score_net_workspace_bytes(int32_t batch);
+
+/*
+ * Features of members m0 .. m0+n-1 from their current states: u_x * u_scale,
+ * u_y * u_scale and (rho - 1) * rho_scale averaged over pool x pool blocks of
+ * the patch x patch cells whose lower-left cell is (px0, py0); rho and u are
+ * those of the step the state belongs to (u = (sum c_i f_i - F/2) / rho from
+ * the post-collision populations); obstacle cells count as rho = 1, u = 0.
+ * out_dev: device float[n][3][patch/pool][patch/pool], patch/pool <= 16.
+ */
+int score_features(const lbm_ctx* ctx, int32_t m0, int32_t n, int32_t px0, int32_t py0, int32_t patch,
+                   int32_t pool, double u_scale, double rho_scale, float* out_dev);
+
+/* y_dev[b] = network(x_dev[b]) for a batch of device float[batch][3][16][16]. */
+int score_net_forward(const float* params_dev, const float* x_dev, int32_t batch, float* y_dev,
+                      void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/*
+ * Gradient of the mean squared error (1/B) sum_b (y_b - label_b)^2 with
+ * respect to every parameter (device float[score_net_params()]), and the loss
+ * into loss_dev (device float, may be NULL).  Deterministic: per-image
+ * contributions are added in image order.
+ */
+int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
+                   float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on FP32 parameters with moments m, v. */
+int score_net_adam(float* params_dev, float* m_dev, float* v_dev, const float* grads_dev, int32_t step,
+                   double lr, double beta1, double beta2, double eps, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);
 

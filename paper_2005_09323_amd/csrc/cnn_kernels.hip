@@ -1,0 +1,458 @@
+// Score network for learned AMS scores: near-wake features, forward and
+// backward of a small CNN on BF16 matrix cores, and Adam.
+//
+// The paper's conclusion proposes learning the AMS score function; the
+// network here maps a 3 x 16 x 16 picture of the near wake (u_x, u_y, rho - 1)
+// to one number: three 3x3 convolutions with 32 channels (zero padding,
+// ReLU), a global average and a linear read-out.
+//
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x16_bf16: BF16
+// operands rounded to nearest-even from FP32, FP32 accumulation.  One
+// workgroup (4 waves) owns one image; activations live in LDS as padded
+// 18 x 18 x C tiles (channel fastest), weights as [K][32] with
+// K = (tap, input channel).  Weight gradients are written per image and summed
+// in image order afterwards, so every result is deterministic.
+#include "cnn_kernels.hpp"
+
+namespace lbm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NC = 32;   // channels of every hidden layer
+constexpr int PADW = 18; // padded image side
+constexpr int PAD_ELEMS = PADW * PADW * NC;
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ unsigned short f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Lane layout of the 16x16x16 BF16 MFMA: lane l supplies A[l % 16][4 (l / 16) + j]
+// and B[4 (l / 16) + j][l % 16] (j = 0..3) and receives D[4 (l / 16) + j][l % 16].
+
+// Weights of one layer into LDS as wt[k][o], k = tap * cin + c, zero rows up to kp.
+__device__ void load_weights(const float* __restrict__ w, int cin, int kp, unsigned short* wt) {
+    const int k_real = 9 * cin;
+    for (int e = (int)threadIdx.x; e < kp * NC; e += (int)blockDim.x) {
+        const int k = e / NC, o = e - k * NC;
+        float v = 0.0f;
+        if (k < k_real) {
+            const int tap = k / cin, c = k - tap * cin;
+            v = w[(o * cin + c) * 9 + tap];
+        }
+        wt[e] = f2bf(v);
+    }
+}
+
+__device__ void zero_lds(unsigned short* p, int n) {
+    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) p[e] = 0;
+}
+
+// acc[mt][nt] += conv of the padded input: output pixel (y = 4 wave + mt,
+// x = 4 (l/16) + j), channel o = 16 nt + l % 16.
+template <int CIN, int CSTRIDE>
+__device__ void conv_fwd(const unsigned short* in, const unsigned short* wt, f32x4 acc[4][2], int wave, int lane) {
+    constexpr int K = 9 * CIN;
+    constexpr int KP = (K + 15) / 16 * 16;
+    const int col = lane & 15, kq = (lane >> 4) * 4;
+    for (int ks = 0; ks < KP / 16; ++ks) {
+        bf16x4 bfr[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bfr[nt][j] = (short)wt[(ks * 16 + kq + j) * NC + nt * 16 + col];
+        int tap[4], ch[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = ks * 16 + kq + j;
+            tap[j] = k < K ? k / CIN : -1;
+            ch[j] = k < K ? k - (k / CIN) * CIN : 0;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int y = wave * 4 + mt;
+            bf16x4 afr;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                short v = 0;
+                if (tap[j] >= 0) {
+                    const int dy = tap[j] / 3, dx = tap[j] - 3 * (tap[j] / 3);
+                    v = (short)in[((y + dy) * PADW + (col + dx)) * CSTRIDE + ch[j]];
+                }
+                afr[j] = v;
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(afr, bfr[nt], acc[mt][nt]);
+        }
+    }
+}
+
+// Data gradient of a 32 -> 32 convolution: dX[p][c] = sum_{tap, o} dZ[p - tap + 1][o] W[o][c][tap],
+// from the padded dZ tile and the forward weight table (wt[(tap*32 + c)*32 + o]).
+__device__ void conv_dgrad(const unsigned short* dz, const unsigned short* wt, f32x4 acc[4][2], int wave, int lane) {
+    const int col = lane & 15, kq = (lane >> 4) * 4;
+    for (int ks = 0; ks < 9 * NC / 16; ++ks) {
+        bf16x4 bfr[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = ks * 16 + kq + j;
+                const int tap = k / NC, o = k - tap * NC;
+                bfr[nt][j] = (short)wt[(tap * NC + nt * 16 + col) * NC + o];
+            }
+        const int tap0 = (ks * 16) / NC;  // all 16 k of a step share one tap
+        const int dy = tap0 / 3, dx = tap0 - 3 * (tap0 / 3);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int y = wave * 4 + mt;
+            bf16x4 afr;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = (ks * 16 + kq + j) - tap0 * NC;
+                afr[j] = (short)dz[((y - dy + 2) * PADW + (col - dx + 2)) * NC + o];
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(afr, bfr[nt], acc[mt][nt]);
+        }
+    }
+}
+
+// Weight gradient of one image: dW[o][c][tap] = sum_p dZ[p][o] X[p + tap - 1][c],
+// a GEMM over the 256 pixels; written (not added) to out in canonical order.
+template <int CIN, int CSTRIDE>
+__device__ void conv_wgrad(const unsigned short* dz, const unsigned short* xin, float* __restrict__ out, int wave,
+                           int lane) {
+    constexpr int K = 9 * CIN;
+    constexpr int KP = (K + 15) / 16 * 16;
+    constexpr int TILES = 2 * (KP / 16);
+    const int col = lane & 15, kq = (lane >> 4) * 4;
+    for (int tile = wave; tile < TILES; tile += 4) {
+        const int ot = tile & 1, kt = tile >> 1;
+        const int kk = kt * 16 + col;
+        const int tap = kk < K ? kk / CIN : 0, c = kk < K ? kk - (kk / CIN) * CIN : 0;
+        const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int py = 0; py < 16; ++py) {
+            bf16x4 afr, bfr;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int px = kq + j;
+                afr[j] = (short)dz[((py + 1) * PADW + (px + 1)) * NC + ot * 16 + col];
+                bfr[j] = kk < K ? (short)xin[((py + dy) * PADW + (px + dx)) * CSTRIDE + c] : (short)0;
+            }
+            acc = mfma16(afr, bfr, acc);
+        }
+        if (kk < K) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = ot * 16 + kq + j;
+                out[(o * CIN + c) * 9 + tap] = acc[j];
+            }
+        }
+    }
+}
+
+// Deterministic per-channel totals of values held in the accumulator layout.
+__device__ void channel_sum(const float v[4][2][4], float* red, float* out, int wave, int lane) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        float s = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s += v[mt][nt][j];
+        red[(wave * 4 + (lane >> 4)) * NC + nt * 16 + (lane & 15)] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        float tot = 0.0f;
+        for (int q = 0; q < 16; ++q) tot += red[q * NC + threadIdx.x];
+        out[threadIdx.x] = tot;
+    }
+    __syncthreads();
+}
+
+// Padded tile of an input image x[b] (FP32 [3][16][16], NCHW) with 4 channel slots.
+__device__ void load_input(const float* __restrict__ x, unsigned short* buf) {
+    zero_lds(buf, PADW * PADW * 4);
+    __syncthreads();
+    for (int e = (int)threadIdx.x; e < 3 * 256; e += (int)blockDim.x) {
+        const int c = e / 256, p = e - c * 256, y = p / 16, xx = p - y * 16;
+        buf[((y + 1) * PADW + (xx + 1)) * 4 + c] = f2bf(x[e]);
+    }
+}
+
+// Padded tile of a saved activation ([256][32] BF16).
+__device__ void load_act(const unsigned short* __restrict__ act, unsigned short* buf) {
+    zero_lds(buf, PAD_ELEMS);
+    __syncthreads();
+    for (int e = (int)threadIdx.x; e < 256 * NC; e += (int)blockDim.x) {
+        const int p = e / NC, c = e - p * NC, y = p / 16, xx = p - y * 16;
+        buf[((y + 1) * PADW + (xx + 1)) * NC + c] = act[e];
+    }
+}
+
+// Bias, ReLU and store of a layer output (accumulator layout) into a padded
+// tile and, if act is given, into the saved activation.
+__device__ void relu_store(f32x4 acc[4][2], const float* __restrict__ bias, unsigned short* tile,
+                           unsigned short* __restrict__ act, float vals[4][2][4], int wave, int lane) {
+    const int col = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
+                const float a = fmaxf(acc[mt][nt][j] + bias[o], 0.0f);
+                vals[mt][nt][j] = a;
+                const unsigned short b = f2bf(a);
+                if (tile) tile[((y + 1) * PADW + (x + 1)) * NC + o] = b;
+                if (act) act[(y * 16 + x) * NC + o] = b;
+            }
+}
+
+__device__ void zero_acc(f32x4 acc[4][2]) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+__global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
+    __shared__ unsigned short buf0[PAD_ELEMS];
+    __shared__ unsigned short buf1[PAD_ELEMS];
+    __shared__ unsigned short wt[9 * NC * NC];
+    __shared__ float red[16 * NC];
+    __shared__ float gsum[NC];
+    const int b = (int)blockIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const float* p = a.params;
+    unsigned short* act = a.act ? a.act + (long long)b * 3 * 256 * NC : nullptr;
+    f32x4 acc[4][2];
+    float vals[4][2][4];
+
+    load_input(a.x + (long long)b * 3 * 256, buf0);
+    load_weights(p + CNN_OFF_W1, 3, 32, wt);
+    zero_lds(buf1, PAD_ELEMS);
+    __syncthreads();
+    zero_acc(acc);
+    conv_fwd<3, 4>(buf0, wt, acc, wave, lane);
+    relu_store(acc, p + CNN_OFF_B1, buf1, act, vals, wave, lane);
+    __syncthreads();
+
+    load_weights(p + CNN_OFF_W2, NC, 9 * NC, wt);
+    zero_lds(buf0, PAD_ELEMS);
+    __syncthreads();
+    zero_acc(acc);
+    conv_fwd<NC, NC>(buf1, wt, acc, wave, lane);
+    relu_store(acc, p + CNN_OFF_B2, buf0, act ? act + 256 * NC : nullptr, vals, wave, lane);
+    __syncthreads();
+
+    load_weights(p + CNN_OFF_W3, NC, 9 * NC, wt);
+    __syncthreads();
+    zero_acc(acc);
+    conv_fwd<NC, NC>(buf0, wt, acc, wave, lane);
+    relu_store(acc, p + CNN_OFF_B3, nullptr, act ? act + 2 * 256 * NC : nullptr, vals, wave, lane);
+    channel_sum(vals, red, gsum, wave, lane);
+    if (threadIdx.x == 0) {
+        float y = p[CNN_OFF_B4];
+        for (int o = 0; o < NC; ++o) {
+            const float g = gsum[o] * (1.0f / 256.0f);
+            if (a.gap) a.gap[(long long)b * NC + o] = g;
+            y += g * p[CNN_OFF_W4 + o];
+        }
+        a.y[b] = y;
+    }
+}
+
+// Backward of one image given the saved activations; writes the image's
+// parameter gradients (all but w4, b4) into partial[b][*].
+__global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
+    __shared__ unsigned short bufx[PAD_ELEMS];
+    __shared__ unsigned short bufd[PAD_ELEMS];
+    __shared__ unsigned short wt[9 * NC * NC];
+    __shared__ float red[16 * NC];
+    __shared__ float dsum[NC];
+    __shared__ float dg[NC];
+    const int b = (int)blockIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int col = lane & 15, kq = (lane >> 4) * 4;
+    const float* p = a.params;
+    const unsigned short* act = a.act + (long long)b * 3 * 256 * NC;
+    float* part = a.partial + (long long)b * CNN_N_PARAMS;
+    // dL/dy for the mean squared error, then through the read-out and the average
+    const float gy = 2.0f * (a.y[b] - a.labels[b]) / (float)a.batch;
+    if (threadIdx.x < NC) dg[threadIdx.x] = gy * p[CNN_OFF_W4 + threadIdx.x] * (1.0f / 256.0f);
+
+    // ---- layer 3: dZ3 = mask(a3) * dG / 256
+    load_act(act + 256 * NC, bufx);  // a2, input of layer 3
+    load_weights(p + CNN_OFF_W3, NC, 9 * NC, wt);
+    zero_lds(bufd, PAD_ELEMS);
+    __syncthreads();
+    float vals[4][2][4];
+    const unsigned short* a3 = act + 2 * 256 * NC;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
+                const float d = bf2f(a3[(y * 16 + x) * NC + o]) > 0.0f ? dg[o] : 0.0f;
+                vals[mt][nt][j] = d;
+                bufd[((y + 1) * PADW + (x + 1)) * NC + o] = f2bf(d);
+            }
+    channel_sum(vals, red, dsum, wave, lane);  // includes the barrier before dZ3 is read
+    if (threadIdx.x < NC) part[CNN_OFF_B3 + threadIdx.x] = dsum[threadIdx.x];
+    conv_wgrad<NC, NC>(bufd, bufx, part + CNN_OFF_W3, wave, lane);
+    f32x4 acc[4][2];
+    zero_acc(acc);
+    conv_dgrad(bufd, wt, acc, wave, lane);
+    __syncthreads();
+    // ---- layer 2: dZ2 = mask(a2) * dA2
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
+                const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * NC + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
+                vals[mt][nt][j] = d;
+                bufd[((y + 1) * PADW + (x + 1)) * NC + o] = f2bf(d);
+            }
+    channel_sum(vals, red, dsum, wave, lane);
+    if (threadIdx.x < NC) part[CNN_OFF_B2 + threadIdx.x] = dsum[threadIdx.x];
+    load_act(act, bufx);  // a1 (load_act zeroes then fills; its first barrier orders the reuse)
+    load_weights(p + CNN_OFF_W2, NC, 9 * NC, wt);
+    __syncthreads();
+    conv_wgrad<NC, NC>(bufd, bufx, part + CNN_OFF_W2, wave, lane);
+    zero_acc(acc);
+    conv_dgrad(bufd, wt, acc, wave, lane);
+    __syncthreads();
+    // ---- layer 1: dZ1 = mask(a1) * dA1
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
+                const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * NC + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
+                vals[mt][nt][j] = d;
+                bufd[((y + 1) * PADW + (x + 1)) * NC + o] = f2bf(d);
+            }
+    channel_sum(vals, red, dsum, wave, lane);
+    if (threadIdx.x < NC) part[CNN_OFF_B1 + threadIdx.x] = dsum[threadIdx.x];
+    load_input(a.x + (long long)b * 3 * 256, bufx);
+    __syncthreads();
+    conv_wgrad<3, 4>(bufd, bufx, part + CNN_OFF_W1, wave, lane);
+}
+
+// Gradients summed over the batch in image order; the read-out's own
+// gradients (w4, b4) and the loss from the saved averages.
+__global__ __launch_bounds__(256) void cnn_reduce_kernel(CnnArgs a) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= CNN_N_PARAMS) return;
+    float tot = 0.0f;
+    if (q >= CNN_OFF_W4) {
+        for (int b = 0; b < a.batch; ++b) {
+            const float gy = 2.0f * (a.y[b] - a.labels[b]) / (float)a.batch;
+            tot += q == CNN_OFF_B4 ? gy : gy * a.gap[(long long)b * NC + (q - CNN_OFF_W4)];
+        }
+    } else {
+        for (int b = 0; b < a.batch; ++b) tot += a.partial[(long long)b * CNN_N_PARAMS + q];
+    }
+    a.grads[q] = tot;
+    if (q == 0 && a.loss) {
+        double l = 0.0;
+        for (int b = 0; b < a.batch; ++b) {
+            const double r = (double)a.y[b] - (double)a.labels[b];
+            l += r * r;
+        }
+        *a.loss = (float)(l / a.batch);
+    }
+}
+
+// Adam (Kingma & Ba) on the FP32 master weights, bias-corrected.
+__global__ __launch_bounds__(256) void cnn_adam_kernel(AdamArgs a) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= CNN_N_PARAMS) return;
+    const double g = a.grads[q];
+    const double m = a.beta1 * a.m[q] + (1.0 - a.beta1) * g;
+    const double v = a.beta2 * a.v[q] + (1.0 - a.beta2) * g * g;
+    a.m[q] = (float)m;
+    a.v[q] = (float)v;
+    const double mh = m / (1.0 - pow(a.beta1, (double)a.step));
+    const double vh = v / (1.0 - pow(a.beta2, (double)a.step));
+    a.params[q] = (float)((double)a.params[q] - a.lr * mh / (sqrt(vh) + a.eps));
+}
+
+// Near-wake features of members m0 .. m0+n-1: block = member, thread = pooled pixel.
+__global__ __launch_bounds__(256) void features_kernel(FeatureArgs a) {
+    const int mi = a.m0 + (int)blockIdx.x;
+    const MemberDev m = a.members[mi];
+    const int side = a.patch / a.pool;
+    const int t = (int)threadIdx.x;
+    if (t >= side * side) return;
+    const int oy = t / side, ox = t - oy * side;
+    const float* st = (a.parity[mi] ? a.pop1 : a.pop0) + m.off;
+    const long long plane = (long long)m.nx * m.ny;
+    double su = 0.0, sv = 0.0, sr = 0.0;
+    for (int yy = 0; yy < a.pool; ++yy)
+        for (int xx = 0; xx < a.pool; ++xx) {
+            const int y = a.py0 + oy * a.pool + yy, x = a.px0 + ox * a.pool + xx;
+            if (in_square(m, x, y)) continue;  // rho = 1, u = 0 inside the obstacle
+            const long long c = (long long)y * m.nx + x;
+            double d[9];
+            for (int i = 0; i < 9; ++i) d[i] = (double)st[i * plane + c];
+            const double drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+            const double jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
+            const double jy = ((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8]);
+            const double rho = 1.0 + drho;
+            // post-collision momentum carries the step's force: u = (j - F/2) / rho
+            su += (jx - m.half_fx) / rho;
+            sv += jy / rho;
+            sr += drho;
+        }
+    const double inv = 1.0 / (double)(a.pool * a.pool);
+    float* out = a.out + (long long)blockIdx.x * 3 * side * side;
+    out[t] = (float)(su * inv * a.u_scale);
+    out[side * side + t] = (float)(sv * inv * a.u_scale);
+    out[2 * side * side + t] = (float)(sr * inv * a.rho_scale);
+}
+
+hipError_t launch_cnn_forward(const CnnArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(cnn_forward_kernel, dim3(a.batch), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_cnn_backward(const CnnArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(cnn_backward_kernel, dim3(a.batch), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((CNN_N_PARAMS + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_cnn_adam(const AdamArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(cnn_adam_kernel, dim3((CNN_N_PARAMS + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_features(const FeatureArgs& a, int n, hipStream_t st) {
+    hipLaunchKernelGGL(features_kernel, dim3(n), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -140,6 +140,15 @@ class Ensemble:
                                                 _ptr(anc), _ptr(lnr)))
         return anc, lnr
 
+    def features(self, m0: int, n: int, px0: int, py0: int, patch: int, pool: int,
+                 u_scale: float, rho_scale: float) -> torch.Tensor:
+        """Near-wake feature pictures [n, 3, patch/pool, patch/pool] of members m0 .. m0+n-1."""
+        side = patch // pool
+        out = torch.empty((n, 3, side, side), dtype=torch.float32, device=self.device)
+        native.check(self.lib.score_features(self._ctx, m0, n, px0, py0, patch, pool, u_scale, rho_scale,
+                                             _ptr(out)))
+        return out
+
     def perturb(self, mask: Sequence[int], key: int, period: int, eps: float, snapshots: torch.Tensor) -> None:
         arr = (ctypes.c_int32 * self.n)(*[int(bool(a)) for a in mask])
         native.check(self.lib.lbm_perturb(self._ctx, arr, key, period, eps, _ptr(snapshots),
@@ -173,3 +182,55 @@ def ams_score_kill_branch(series: torch.Tensor, n_kill: int, key: int, iteration
     k = int(n_killed.item())
     return dict(killed=killed[:k], parents=parent[:k], branch_t=branch_t[:k], level=float(level.item()),
                 maxima=maxima, n_killed=k)
+
+
+class ScoreNet:
+    """The learned AMS score network: FP32 master parameters on the device, BF16 matrix-core kernels."""
+
+    def __init__(self, params: torch.Tensor, max_batch: int, device: str = "cuda"):
+        self.lib = native.lib()
+        self.n_params = self.lib.score_net_params()
+        if params.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {params.numel()}")
+        self.params = params.detach().to(device=device, dtype=torch.float32).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.step_count = 0
+        self.max_batch = max_batch
+        nbytes = self.lib.score_net_workspace_bytes(max_batch)
+        self.workspace = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=device)
+        self._ws_bytes = nbytes
+
+    def _check(self, x: torch.Tensor) -> int:
+        if x.dim() != 4 or tuple(x.shape[1:]) != (3, 16, 16) or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float32 [B, 3, 16, 16] tensor")
+        if x.shape[0] > self.max_batch:
+            raise ValueError("batch larger than max_batch")
+        return int(x.shape[0])
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        b = self._check(x)
+        y = torch.empty(b, dtype=torch.float32, device=x.device)
+        native.check(self.lib.score_net_forward(_ptr(self.params), _ptr(x), b, _ptr(y), _ptr(self.workspace),
+                                                self._ws_bytes, _stream_handle(None)))
+        return y
+
+    def grad(self, x: torch.Tensor, labels: torch.Tensor) -> torch.Tensor:
+        """Gradient of the mean squared error into self.grads (returned); the loss into self.loss."""
+        b = self._check(x)
+        native.check(self.lib.score_net_grad(_ptr(self.params), _ptr(x), _ptr(labels.contiguous()), b,
+                                             _ptr(self.grads), _ptr(self.loss), _ptr(self.workspace),
+                                             self._ws_bytes, _stream_handle(None)))
+        return self.grads
+
+    def adam(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+        self.step_count += 1
+        native.check(self.lib.score_net_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(self.grads),
+                                             self.step_count, lr, beta1, beta2, eps, _stream_handle(None)))
+
+    def train_step(self, x: torch.Tensor, labels: torch.Tensor, lr: float = 1e-3) -> torch.Tensor:
+        self.grad(x, labels)
+        self.adam(lr)
+        return self.loss

@@ -61,6 +61,12 @@ _SIG = {
     "lbm_copy_state_in": (ctypes.c_int, [_P, _I, _P, _I]),
     "ams_score_kill_branch": (ctypes.c_int, [_P, _I, _I, _I, _U64, _I, _P, _P, _P, _P, _P, _P, _P]),
     "lbm_window_mean": (ctypes.c_int, [_P, _I, _I, _I, _I, _P, _P]),
+    "score_net_params": (_I, []),
+    "score_net_workspace_bytes": (ctypes.c_size_t, [_I]),
+    "score_features": (ctypes.c_int, [_P, _I, _I, _I, _I, _I, _I, _D, _D, _P]),
+    "score_net_forward": (ctypes.c_int, [_P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
+    "score_net_grad": (ctypes.c_int, [_P, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
+    "score_net_adam": (ctypes.c_int, [_P, _P, _P, _P, _I, _D, _D, _D, _D, _P]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -86,7 +92,7 @@ def declared_functions() -> list:
     """Names of the functions ``include/lbm.h`` declares."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_\w+|gktl_\w+|ams_\w+)\s*\(", text)) - {"lbm_ctx"})
+    return sorted(set(re.findall(r"\b(lbm_\w+|gktl_\w+|ams_\w+|score_\w+)\s*\(", text)) - {"lbm_ctx"})
 
 
 def check(rc: int) -> None:

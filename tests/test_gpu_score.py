@@ -1,0 +1,166 @@
+"""GPU parity of the learned score: features, network forward/backward on BF16
+matrix cores, Adam.
+
+The oracle runs in FP64 on the same BF16-rounded weights and inputs; the GPU
+also rounds each hidden layer's activations (and gradients) to BF16 before
+the next matrix-core product, so network outputs and gradients are compared
+by relative L2 norm per tensor: <= 1e-2 (outputs) and <= 3e-2 (gradients),
+a few BF16 roundings (2^-8 each) deep.  Features and Adam are FP32/FP64
+elementwise: <= 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import cnn as ocnn
+from oracle import features as ofeat
+from oracle import lbm as olbm
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4")
+
+
+def _flat(p):
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).ravel() for k in NAMES])
+
+
+def _unflat(v):
+    shp = ocnn.shapes()
+    out, off = {}, 0
+    for k in NAMES:
+        n = int(np.prod(shp[k])) if shp[k] else 1
+        out[k] = v[off:off + n].reshape(shp[k]) if shp[k] else np.array(v[off])
+        off += n
+    return out
+
+
+def _bf16(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float64)).float().bfloat16().double().numpy()
+
+
+def _bf16_params(p):
+    """Weights as the matrix cores see them (BF16); biases and the read-out stay FP32."""
+    q = {}
+    for k in NAMES:
+        v = np.asarray(p[k], dtype=np.float32).astype(np.float64)
+        q[k] = _bf16(v) if k in ("w1", "w2", "w3") else v
+    return q
+
+
+def _net(params_flat, max_batch):
+    from paper_2005_09323_amd.ensemble import ScoreNet
+    return ScoreNet(torch.from_numpy(params_flat.astype(np.float32)), max_batch)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+@pytest.mark.parametrize("batch", [1, 7, 64])
+def test_forward_matches_oracle(batch):
+    p = workloads.cnn_params(11)
+    x, _ = workloads.cnn_batch(batch, 12)
+    net = _net(_flat(p), batch)
+    y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
+    ref, _ = ocnn.forward(_bf16_params(p), _bf16(x.astype(np.float32)))
+    assert _rel_l2(y, ref) <= 1e-2, _rel_l2(y, ref)
+
+
+def test_gradients_match_oracle():
+    p = workloads.cnn_params(21)
+    x, lab = workloads.cnn_batch(16, 22)
+    net = _net(_flat(p), 16)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    lt = torch.from_numpy(lab.astype(np.float32)).cuda()
+    g = net.grad(xt, lt).cpu().numpy().astype(np.float64)
+    qp = _bf16_params(p)
+    xb = _bf16(x.astype(np.float32))
+    y, cache = ocnn.forward(qp, xb)
+    ref = ocnn.backward(qp, cache, y, lab.astype(np.float32).astype(np.float64))
+    gg = _unflat(g)
+    for k in NAMES:
+        err = _rel_l2(gg[k], ref[k])
+        assert err <= 3e-2, (k, err)
+    loss_ref = ocnn.loss(y, lab.astype(np.float32).astype(np.float64))
+    assert abs(net.loss.item() / loss_ref - 1) < 1e-2
+
+
+def test_zero_network_gives_bias_and_deterministic():
+    p = {k: np.zeros_like(v) for k, v in workloads.cnn_params(0).items()}
+    p["b4"] = np.array(0.375)
+    x, lab = workloads.cnn_batch(5, 1)
+    net = _net(_flat(p), 5)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    assert torch.all(net.forward(xt) == 0.375)
+    p2 = workloads.cnn_params(3)
+    net2 = _net(_flat(p2), 32)
+    xb, lb = workloads.cnn_batch(32, 4)
+    xt2 = torch.from_numpy(xb.astype(np.float32)).cuda()
+    lt2 = torch.from_numpy(lb.astype(np.float32)).cuda()
+    g1 = net2.grad(xt2, lt2).clone()
+    g2 = net2.grad(xt2, lt2).clone()
+    assert torch.equal(g1, g2)
+    y_all = net2.forward(xt2)
+    y_one = torch.cat([net2.forward(xt2[i:i + 1].contiguous()) for i in range(32)])
+    assert torch.equal(y_all, y_one)
+
+
+def test_adam_matches_oracle_step():
+    p = workloads.cnn_params(5)
+    flat = _flat(p).astype(np.float32)
+    net = _net(flat.astype(np.float64), 4)
+    rng = np.random.default_rng(3)
+    opt = ocnn.Adam(lr=1e-3)
+    ref = {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in _unflat(flat.astype(np.float64)).items()}
+    for _ in range(3):
+        g = rng.standard_normal(len(flat)).astype(np.float32)
+        net.grads.copy_(torch.from_numpy(g))
+        net.adam(lr=1e-3)
+        opt.step(ref, _unflat(g.astype(np.float64)))
+    got = net.params.cpu().numpy().astype(np.float64)
+    assert np.abs(got - _flat(ref)).max() < 1e-6
+
+
+def test_training_reduces_loss_like_oracle():
+    p = workloads.cnn_params(7)
+    x, _ = workloads.cnn_batch(6, 8)
+    lab = 10 * x[:, 0].mean(axis=(1, 2))
+    net = _net(_flat(p), 6)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    lt = torch.from_numpy(lab.astype(np.float32)).cuda()
+    gpu_loss = [net.train_step(xt, lt, lr=1e-3).item() for _ in range(25)]
+    ref = _bf16_params(p)
+    opt = ocnn.Adam(lr=1e-3)
+    ref_loss = []
+    for _ in range(25):
+        y, c = ocnn.forward(ref, _bf16(x.astype(np.float32)))
+        ref_loss.append(ocnn.loss(y, lab))
+        opt.step(ref, ocnn.backward(ref, c, y, lab))
+    assert gpu_loss[-1] < 0.5 * gpu_loss[0]
+    assert abs(gpu_loss[-1] / ref_loss[-1] - 1) < 0.15, (gpu_loss[-1], ref_loss[-1])
+
+
+def test_features_match_oracle():
+    from paper_2005_09323_amd.ensemble import Ensemble
+    wl = workloads.ams_ensemble(4)
+    m = wl.members[0]
+    ch = olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square)
+    ens = Ensemble(wl.members, series_capacity=8)
+    ens.init(0, 0.0)
+    states = []
+    for i in range(4):
+        f, _ = olbm.run(ch, olbm.init_populations(ch, olbm.init_density(ch, 40 + i, 0, 1e-2)), 2)
+        d = (f - olbm.W[:, None, None]).astype(np.float32)
+        d[:, olbm.solid_mask(ch)] = 0
+        states.append(d)
+        ens.copy_state_in(i, torch.from_numpy(d).cuda(), 1)
+    x0, y0, s = m.square
+    px0, py0 = x0 + s - 8, y0 + s // 2 - 32  # overlaps the square's last columns
+    got = ens.features(0, 4, px0, py0, 64, 4, 20.0, 200.0).cpu().numpy()
+    for i in range(4):
+        f = states[i].astype(np.float64) + olbm.W[:, None, None]
+        f[:, olbm.solid_mask(ch)] = 0
+        ref = ofeat.near_wake(ch, f, px0, py0, 64, 4, 20.0, 200.0)
+        assert np.abs(got[i] - ref).max() <= 1e-6 * np.abs(ref).max() + 1e-9
