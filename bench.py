@@ -78,18 +78,87 @@ def copy_calibration(mib: int, reps: int) -> None:
           flush=True)
 
 
+def _timed(fn, reps=1):
+    """Milliseconds per call of fn on the current stream (HIP events)."""
+    import torch
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def legs():
+    """Secondary measurements of the other rows of the path (one short run each)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2005_09323_amd.ensemble import Ensemble, ScoreNet, ams_score_kill_branch, window_mean
+    out = {}
+    # GKTL: one cloning period of 256 steps on 256 x 1024 x 256, then device selection + clone/perturb
+    wl = workloads.gktl_ensemble()
+    x = wl.extra
+    ens = Ensemble(wl.members, series_capacity=2 * x["period"] + 2)
+    ens.set_tile(0)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.set_observable(0.0, 1e-3, x["dt"])
+    snaps = torch.from_numpy(workloads.snapshot_states(x["n_snap"], wl.members[0], 1)).cuda()
+    ens.step(x["period"])
+    torch.cuda.synchronize()
+    t_steps = _timed(lambda: ens.step(x["period"]))
+    t_clone = _timed(lambda: ens.gktl_select_clone(1.0, 1, 0, x["eps"], snaps))
+    cells = wl.cells
+    out["gktl_period"] = {"workload": wl.name, "period_steps": x["period"], "ms_steps": round(t_steps, 3),
+                          "ms_select_clone": round(t_clone, 3),
+                          "clone_overhead": round(t_clone / t_steps, 5),
+                          "MLUPS_with_cloning": round(cells * x["period"] / ((t_steps + t_clone) / 1e3) / 1e6, 1)}
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    # AMS: selection over 512 members' window-mean scores of 2560-step drag series
+    wl = workloads.ams_ensemble()
+    series = torch.from_numpy(workloads.score_series(len(wl.members), wl.steps, 3)).cuda()
+    t_win = _timed(lambda: window_mean(series, wl.extra["window"]), 3)
+    score = window_mean(series, wl.extra["window"])
+    t_sel = _timed(lambda: ams_score_kill_branch(score, 26, 1, 0), 3)
+    out["ams_selection"] = {"workload": wl.name, "ms_window_mean": round(t_win, 3), "ms_kill_branch": round(t_sel, 3)}
+    # learned score: one training step (forward + backward + Adam) on a batch of 256 pictures
+    p = workloads.cnn_params(1)
+    flat = np.concatenate([np.ravel(p[k]) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4")])
+    net = ScoreNet(torch.from_numpy(flat.astype(np.float32)), 256)
+    xb, lb = workloads.cnn_batch(256, 2)
+    xt = torch.from_numpy(xb.astype(np.float32)).cuda()
+    lt = torch.from_numpy(lb.astype(np.float32)).cuda()
+    net.train_step(xt, lt)
+    t_train = _timed(lambda: net.train_step(xt, lt), 10)
+    t_fwd = _timed(lambda: net.forward(xt), 10)
+    flop_fwd = 256 * 32 * 2 * (27 + 288 + 288)            # per picture, convolutions only
+    flop_train = flop_fwd + 256 * 32 * 2 * (288 + 288) + 256 * 32 * 2 * (27 + 288 + 288)
+    out["score_net"] = {"batch": 256, "ms_train_step": round(t_train, 4), "ms_forward": round(t_fwd, 4),
+                        "pictures_per_s_train": round(256 / (t_train / 1e3), 1),
+                        "mfma_TFLOPs_train": round(256 * flop_train / (t_train / 1e3) / 1e12, 3),
+                        "mfma_TFLOPs_forward": round(256 * flop_fwd / (t_fwd / 1e3) / 1e12, 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ensemble", choices=["ensemble", "mixed", "single"])
-    ap.add_argument("--tile", type=int, default=-1, help="step-kernel tile id (-1: autotune)")
+    ap.add_argument("--tile", type=int, default=0, help="step-kernel launch shape (-1: autotune; 0 is the profiled default)")
     ap.add_argument("--cpu-steps", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_traffic.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_ensemble1024_traffic.json"))
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
                     help="copy: time a plain device copy of --copy-mib MiB (counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=2048)
+    ap.add_argument("--no-legs", action="store_true", help="skip the GKTL / AMS / score-network legs")
     args = ap.parse_args()
     if args.mode == "copy":
         return copy_calibration(args.copy_mib, max(args.steps, 1))
@@ -129,14 +198,16 @@ def main():
     achieved = BYTES_PER_LUP * fluid / (sec / args.steps) / 1e9  # GB/s per step (kernel + reduction)
     flags = int(ens.flags().sum().item())
 
+    # HBM bytes per launch from the committed counter run, valid only while the
+    # kernel source is the one the counters were taken on
     traffic = None
     if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == wl.name:
-                traffic = tj.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+        import hashlib
+        tj = json.load(open(args.traffic_json))
+        src = open(os.path.join(ROOT, "paper_2005_09323_amd", "csrc", "lbm_kernels.hip"), "rb").read()
+        same_kernel = hashlib.sha256(src).hexdigest().startswith(tj.get("kernel_source_sha256_prefix", "-"))
+        if tj.get("workload") == wl.name and same_kernel and tile == 0:
+            traffic = tj.get("bytes_per_launch")
 
     out = {
         "metric": METRIC,
@@ -157,9 +228,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
     }
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    if not args.no_legs:
+        out["legs"] = legs()
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
-    ens.close()
     print(json.dumps(out), flush=True)
 
 
