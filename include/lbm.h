@@ -174,8 +174,9 @@ int lbm_autotune(lbm_ctx* ctx, int32_t n_steps, int32_t* best_tile);
  *   perturbed: f <- f + eps * sum_n alpha_n f^(n) with alpha_n from key
  *   (key, PRTB), counter (m, period, n / 4, 0), word n % 4, then scaled by
  *   one factor that restores its mass before perturbation.
- *   snapshots: device, n_snap states in this library's deviation layout
- *   ([n_snap][9][ny][nx]); may be NULL when eps == 0 or n_snap == 0.
+ *   snapshots: device, n_snap <= 16 states in this library's deviation
+ *   layout ([n_snap][9][ny][nx]), 16-byte aligned; may be NULL when
+ *   eps == 0 or n_snap == 0.
  *   accum is reset to 0; flags are copied from the ancestor.
  * LBM_ENONFINITE if every s_n is non-finite (nothing is changed).  Waits once
  * on the context's stream (after the selection, to read its status).

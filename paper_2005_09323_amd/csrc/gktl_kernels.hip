@@ -180,7 +180,11 @@ __global__ void mass_scale_kernel(ScaleArgs a) {
 //   copy:    d_new = d_src
 //   perturb: d_new = s (d_src + eps sum_n alpha_n d^(n)) + c_w w_i
 // (full populations: f_new = s (f_src + eps sum_n alpha_n f^(n)), f = w + d).
-// blockIdx.y = member; each thread handles 4 consecutive floats.
+// blockIdx.y = member; each thread moves 4 consecutive floats with 16-byte
+// accesses when the member block allows it (a plane of a multiple-of-4
+// width never splits a vector between two directions).
+typedef float f4g __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void clone_gather_kernel(GatherArgs a) {
     const int m = (int)blockIdx.y;
     const int mode = a.mode[m];
@@ -193,6 +197,28 @@ __global__ __launch_bounds__(256) void clone_gather_kernel(GatherArgs a) {
     const int src = a.src[m];
     const float* sp = (a.parity[src] ? a.pop1 : a.pop0) + a.members[src].off;
     float* dp = (a.parity[m] ? a.pop0 : a.pop1) + md.off;
+    const bool vec = (plane & 3) == 0;
+    if (vec) {
+        const f4g v = *(const f4g*)(sp + e0);
+        if (mode == MODE_COPY) {
+            __builtin_nontemporal_store(v, (f4g*)(dp + e0));
+            return;
+        }
+        const int i = (int)(e0 / plane);
+        f4g acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        double ad[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < a.n_snap; ++q) {
+            const double al = a.alpha[(long long)m * MAX_SNAP + q];
+            const f4g sv = *(const f4g*)(a.snapshots + (long long)q * total + e0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ad[k] += al * (double)sv[k];
+        }
+        const double s = a.scale[m], cw = a.coef_w[m] * WD[i], eps = a.eps;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = (float)(s * ((double)v[k] + eps * ad[k]) + cw);
+        *(f4g*)(dp + e0) = acc;
+        return;
+    }
     const int cnt = (int)min((long long)4, total - e0);
     if (mode == MODE_COPY) {
         for (int k = 0; k < cnt; ++k) dp[e0 + k] = sp[e0 + k];

@@ -118,6 +118,7 @@ static int check_snapshots(const lbm_ctx* c, double eps, const float* snapshots,
     if (!std::isfinite(eps)) return lbm_fail(LBM_EINVAL, "eps must be finite");
     if (n_snap < 0 || n_snap > MAX_SNAP) return lbm_fail(LBM_EINVAL, "n_snap must be in [0, %d]", MAX_SNAP);
     if (eps != 0.0 && n_snap > 0 && !snapshots) return lbm_fail(LBM_EINVAL, "snapshots are NULL");
+    if ((uintptr_t)snapshots & 15) return lbm_fail(LBM_EINVAL, "snapshots must be 16-byte aligned");
     if (!c->uniform_shape) return lbm_fail(LBM_EUNSUPPORTED, "cloning needs every member on one lattice shape");
     return LBM_OK;
 }
