@@ -115,6 +115,11 @@ int lbm_destroy(lbm_ctx* ctx);
  */
 int lbm_init(lbm_ctx* ctx, uint64_t seed, double noise_amp);
 
+/* As lbm_init, but the populations start at the equilibrium of density rho and
+   the uniform velocity (ux0, 0), |ux0| <= 0.3 (ux0 = 0 is lbm_init).  Used to
+   start a channel flow near its developed speed instead of at rest. */
+int lbm_init_flow(lbm_ctx* ctx, uint64_t seed, double noise_amp, double ux0);
+
 /* Observable weighed by GKTL: A(t) = (f_d(t) - mu)/sigma, integrated with step dt. */
 int lbm_set_observable(lbm_ctx* ctx, double mu, double sigma, double dt);
 

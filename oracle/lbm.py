@@ -216,10 +216,13 @@ def init_density(ch: Channel, seed: int, member: int, amp: float) -> np.ndarray:
     return rho
 
 
-def init_populations(ch: Channel, rho: np.ndarray) -> np.ndarray:
-    """Equilibrium at rest with density rho: f_i = w_i rho; zeros on solid cells."""
-    f = W[:, None, None] * rho[None, :, :]
-    f = f.copy()
+def init_populations(ch: Channel, rho: np.ndarray, ux0: float = 0.0) -> np.ndarray:
+    """Equilibrium with density rho and uniform velocity (ux0, 0): f_i = f_i^eq(rho, u0)
+    (w_i rho at rest); zeros on solid cells."""
+    if ux0 == 0.0:
+        f = (W[:, None, None] * rho[None, :, :]).copy()
+    else:
+        f = equilibrium(rho, np.full_like(rho, ux0), np.zeros_like(rho))
     f[:, solid_mask(ch)] = 0.0
     return f
 

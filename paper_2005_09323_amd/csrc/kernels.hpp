@@ -39,6 +39,7 @@ struct InitArgs {
     double* partial;
     uint64_t seed;
     double noise_amp;
+    double ux0;  // initial uniform x-velocity
 };
 
 struct FinalizeArgs {

@@ -259,10 +259,13 @@ static FinalizeArgs finalize_args(lbm_ctx* c, int n, int accumulate, int advance
     return f;
 }
 
-extern "C" int lbm_init(lbm_ctx* c, uint64_t seed, double noise_amp) {
+extern "C" int lbm_init(lbm_ctx* c, uint64_t seed, double noise_amp) { return lbm_init_flow(c, seed, noise_amp, 0.0); }
+
+extern "C" int lbm_init_flow(lbm_ctx* c, uint64_t seed, double noise_amp, double ux0) {
     if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     if (!std::isfinite(noise_amp) || noise_amp < 0 || noise_amp >= 0.5)
         return lbm_fail(LBM_EINVAL, "noise_amp must be in [0, 0.5)");
+    if (!std::isfinite(ux0) || std::fabs(ux0) > 0.3) return lbm_fail(LBM_EINVAL, "|ux0| must be <= 0.3");
     hipError_t e;
     if ((e = fill_int(c->d_parity, c->n, 0, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_cursor, c->n, 0, c->stream)) != hipSuccess ||
@@ -278,6 +281,7 @@ extern "C" int lbm_init(lbm_ctx* c, uint64_t seed, double noise_amp) {
     a.partial = c->d_partial;
     a.seed = seed;
     a.noise_amp = noise_amp;
+    a.ux0 = ux0;
     if ((e = launch_init(a, c->n, c->max_cells, c->stream)) != hipSuccess) return lbm_hip_fail(e, "init kernel");
     if ((e = launch_finalize(finalize_args(c, 1, 0, 0), c->n, c->stream)) != hipSuccess)
         return lbm_hip_fail(e, "drag reduction");

@@ -263,7 +263,8 @@ __global__ __launch_bounds__(64 * TYT) void step_kernel(StepArgs a) {
     }
 }
 
-// Step 0: equilibrium at rest with the seeded density, relaxed once.
+// Step 0: equilibrium with the seeded density and a uniform velocity
+// (u_x0, 0) (at rest for u_x0 = 0), relaxed once.
 __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const int mi = (int)blockIdx.y;
     const MemberDev m = a.members[mi];
@@ -277,9 +278,14 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         const U64x4 w = philox4x64_10((uint64_t)cell, (uint64_t)mi, 0, 0, a.seed, PURPOSE_INIT);
         drho = a.noise_amp * (2.0 * uniform53(w.v[0]) - 1.0);
     }
+    // f_i = f_i^eq(rho, u0) - w_i = w_i [drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)]
+    const double rho = 1.0 + drho, u0 = a.ux0;
     float d[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = (float)(WD[i] * drho);
+    for (int i = 0; i < 9; ++i) {
+        const double cu = (double)CX[i] * u0;
+        d[i] = (float)(WD[i] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * u0 * u0)));
+    }
     const int ri = ring_index(m, x, y);
     const double drag = bgk_guo(m, d, ri >= 0 ? square_links(m, x, y) : 0u);
     float* dst = a.pop0 + m.off;  // step 0 lives in buffer 0 (parity 0)

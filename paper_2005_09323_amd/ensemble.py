@@ -69,8 +69,11 @@ class Ensemble:
             pass
 
     # -- stepping -----------------------------------------------------------
-    def init(self, seed: int, noise_amp: float) -> None:
-        native.check(self.lib.lbm_init(self._ctx, seed, noise_amp))
+    def init(self, seed: int, noise_amp: float, ux0: float = 0.0) -> None:
+        if ux0 == 0.0:
+            native.check(self.lib.lbm_init(self._ctx, seed, noise_amp))
+        else:
+            native.check(self.lib.lbm_init_flow(self._ctx, seed, noise_amp, ux0))
 
     def step(self, n_steps: int) -> None:
         native.check(self.lib.lbm_step_batch(self._ctx, n_steps))

@@ -44,6 +44,7 @@ _SIG = {
     "lbm_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, _I, _P, _P, ctypes.c_size_t, _P, _I, _P, _P]),
     "lbm_destroy": (ctypes.c_int, [_P]),
     "lbm_init": (ctypes.c_int, [_P, _U64, _D]),
+    "lbm_init_flow": (ctypes.c_int, [_P, _U64, _D, _D]),
     "lbm_set_observable": (ctypes.c_int, [_P, _D, _D, _D]),
     "lbm_set_active": (ctypes.c_int, [_P, _P]),
     "lbm_step_batch": (ctypes.c_int, [_P, _I]),

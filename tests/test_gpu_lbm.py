@@ -210,3 +210,18 @@ def test_capacity_and_argument_errors():
     ens.set_time(1)
     ens.step(3)
     assert ens.time() == 4
+
+
+def test_init_with_uniform_velocity_matches_oracle():
+    m = workloads.Member(512, 128, 0.502, 9e-7, workloads.centred_square(128, 64, 16))
+    steps = 400
+    ens = _ensemble([m, m], steps)
+    ens.init(8, 1e-3, ux0=0.05)
+    ens.step(steps - 1)
+    gpu = ens.drag(0, steps).cpu().numpy()
+    for i in range(2):
+        ch = _channel(m)
+        f0 = olbm.init_populations(ch, olbm.init_density(ch, 8, i, 1e-3), ux0=0.05)
+        fout, ref = olbm.run(ch, f0, steps)
+        assert _rel(gpu[i], ref) <= 1e-5
+        assert _state_err(ens, i, m, fout) <= 1e-4

@@ -206,3 +206,14 @@ def test_init_noise_statistics():
     f = lbm.init_populations(ch, rho)
     assert np.allclose(f.sum(0)[fl], rho[fl], atol=1e-15)
     assert np.all(f[:, ~fl] == 0)
+
+
+def test_uniform_flow_start_moments():
+    ch = lbm.Channel(32, 8, 0.6, 0.0, (10, 2, 3))
+    rho = 1 + 0.01 * np.random.default_rng(0).random((8, 32))
+    f = lbm.init_populations(ch, rho, ux0=0.07)
+    fl = ~lbm.solid_mask(ch)
+    jx, jy = lbm.momentum(f)
+    assert np.allclose(f.sum(0)[fl], rho[fl], atol=1e-15)
+    assert np.allclose(jx[fl], 0.07 * rho[fl], atol=1e-15)
+    assert np.allclose(jy[fl], 0.0, atol=1e-16)
