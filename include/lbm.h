@@ -239,6 +239,42 @@ int lbm_window_mean(const float* series_dev, int32_t n, int32_t ld, int32_t t_le
                     float* out_dev, void* hip_stream);
 
 /*
+ * GKTL estimators (paper Appendix C.1-C.2), FP64 on the device.
+ *
+ * gktl_rebuild: the final trajectory j of a run with n_periods cloning
+ * periods of tau steps is traced back through ancestors_dev ([n_periods][n],
+ * as written by gktl_select_clone: slot m after period i continued slot a_m of
+ * period i).  traj_dev[j] (device float[n][n_periods*tau]) receives its drag
+ * series, rebuilt from series_dev (device float[n][ld]; period i occupies
+ * columns col0 + i*tau .. col0 + (i+1)*tau - 1 of the slot that carried it);
+ * traj_integral_dev[j] the integral of the observable along the lineage (sum
+ * over periods of integrals_dev[i][slot], device double[n_periods][n], in
+ * period order); log_weight_dev[j] = sum_i ln R_i - k * traj_integral[j], the
+ * log of the weight that turns the biased ensemble back into the unbiased law
+ * (the paper prints this weight with the exponent's sign flipped).
+ */
+int gktl_rebuild(const int32_t* ancestors_dev, const double* integrals_dev, const double* ln_r_dev,
+                 const float* series_dev, int32_t ld, int32_t col0, int32_t n, int32_t n_periods, int32_t tau,
+                 double k, float* traj_dev, double* log_weight_dev, double* traj_integral_dev, void* hip_stream);
+
+/*
+ * Largest window mean of each row: fmax_dev[r] = max_t (1/window) sum of
+ * series[r][t-window+1 .. t] over the windows inside the row (paper Section
+ * 3.2, time-averaged drag).  FP64 running sums; prefix_scratch_dev is device
+ * double[rows][len+1].
+ */
+int window_mean_max(const float* series_dev, int32_t rows, int32_t len, int32_t window,
+                    double* prefix_scratch_dev, double* fmax_dev, void* hip_stream);
+
+/*
+ * prob_dev[q] = (1/n) sum_j exp(log_weight_dev[j]) [fmax_dev[j] >= levels_dev[q]],
+ * summed in index order in FP64 (all log-weights 0 gives the direct-sampling
+ * estimate).  The return time follows as r = -(T_a - T) / ln(1 - p).
+ */
+int tail_probability(const double* fmax_dev, const double* log_weight_dev, int32_t n,
+                     const double* levels_dev, int32_t n_levels, double* prob_dev, void* hip_stream);
+
+/*
  * Learned AMS score (the paper's conclusion proposes learning the score
  * function).  A small network maps a 3 x 16 x 16 picture of the near wake to
  * one number: three zero-padded 3x3 convolutions with 32 output channels and

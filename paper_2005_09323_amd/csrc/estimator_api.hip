@@ -1,0 +1,65 @@
+// C-ABI entry points of the GKTL / direct-sampling estimators.
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "api_internal.hpp"
+#include "estimators.hpp"
+
+using namespace lbm;
+
+extern "C" int gktl_rebuild(const int32_t* ancestors_dev, const double* integrals_dev, const double* ln_r_dev,
+                            const float* series_dev, int32_t ld, int32_t col0, int32_t n, int32_t n_periods,
+                            int32_t tau, double k, float* traj_dev, double* log_weight_dev,
+                            double* traj_integral_dev, void* hip_stream) {
+    if (!ancestors_dev || !integrals_dev || !ln_r_dev || !series_dev || !traj_dev || !log_weight_dev ||
+        !traj_integral_dev)
+        return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (n < 1 || n_periods < 1 || n_periods > MAX_PERIODS || tau < 1 || col0 < 0 ||
+        (long long)col0 + (long long)n_periods * tau > ld)
+        return lbm_fail(LBM_EINVAL, "bad sizes");
+    RebuildArgs a;
+    a.ancestors = ancestors_dev;
+    a.integrals = integrals_dev;
+    a.ln_r = ln_r_dev;
+    a.series = series_dev;
+    a.ld = ld;
+    a.col0 = col0;
+    a.n = n;
+    a.n_periods = n_periods;
+    a.tau = tau;
+    a.k = k;
+    a.traj = traj_dev;
+    a.log_weight = log_weight_dev;
+    a.traj_integral = traj_integral_dev;
+    hipError_t e = launch_rebuild(a, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "lineage rebuild");
+}
+
+extern "C" int window_mean_max(const float* series_dev, int32_t rows, int32_t len, int32_t window,
+                               double* prefix_scratch_dev, double* fmax_dev, void* hip_stream) {
+    if (!series_dev || !prefix_scratch_dev || !fmax_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (rows < 1 || window < 1 || len < window) return lbm_fail(LBM_EINVAL, "bad sizes");
+    WindowMaxArgs a;
+    a.series = series_dev;
+    a.len = len;
+    a.window = window;
+    a.prefix = prefix_scratch_dev;
+    a.fmax = fmax_dev;
+    hipError_t e = launch_window_max(a, rows, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "window maximum");
+}
+
+extern "C" int tail_probability(const double* fmax_dev, const double* log_weight_dev, int32_t n,
+                                const double* levels_dev, int32_t n_levels, double* prob_dev, void* hip_stream) {
+    if (!fmax_dev || !log_weight_dev || !levels_dev || !prob_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (n < 1 || n_levels < 1) return lbm_fail(LBM_EINVAL, "bad sizes");
+    TailArgs a;
+    a.fmax = fmax_dev;
+    a.log_weight = log_weight_dev;
+    a.levels = levels_dev;
+    a.n = n;
+    a.n_levels = n_levels;
+    a.prob = prob_dev;
+    hipError_t e = launch_tail(a, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "tail probability");
+}

@@ -1,0 +1,93 @@
+// GKTL estimators on the device (paper Appendix C.1-C.2), in FP64.
+//
+// After a GKTL run the drag series of every slot is a patchwork of the
+// trajectories that occupied the slot in each period.  The final ensemble's
+// trajectories are rebuilt by walking the ancestors back; each carries the
+// time integral of the observable along its lineage and the maximum of its
+// window-averaged drag; the unbiased tail probability is the sum of
+// exp(sum_i ln R_i - k int A) over trajectories above each level.
+#include "estimators.hpp"
+
+namespace lbm {
+
+// Block = final trajectory j.  Lineage slot of each period, the rebuilt drag
+// series and the integral of A along the lineage (added in period order).
+__global__ __launch_bounds__(256) void gktl_rebuild_kernel(RebuildArgs a) {
+    __shared__ int slot[MAX_PERIODS];
+    const int j = (int)blockIdx.x;
+    if (threadIdx.x == 0) {
+        int s = j;
+        for (int i = a.n_periods - 1; i >= 0; --i) {
+            s = a.ancestors[(long long)i * a.n + s];
+            slot[i] = s;
+        }
+        double integ = 0.0;
+        for (int i = 0; i < a.n_periods; ++i) integ += a.integrals[(long long)i * a.n + slot[i]];
+        double lz = 0.0;
+        for (int i = 0; i < a.n_periods; ++i) lz += a.ln_r[i];
+        a.log_weight[j] = lz - a.k * integ;
+        a.traj_integral[j] = integ;
+    }
+    __syncthreads();
+    const int len = a.n_periods * a.tau;
+    for (int t = (int)threadIdx.x; t < len; t += (int)blockDim.x) {
+        const int i = t / a.tau;
+        a.traj[(long long)j * len + t] = a.series[(long long)slot[i] * a.ld + a.col0 + t];
+    }
+}
+
+// Block = trajectory: FP64 running sums in time order, then the largest
+// window mean (1/T) (S_t - S_{t-T}) over the windows inside [0, len).
+__global__ __launch_bounds__(256) void window_max_kernel(WindowMaxArgs a) {
+    const int j = (int)blockIdx.x;
+    const float* row = a.series + (long long)j * a.len;
+    double* pre = a.prefix + (long long)j * (a.len + 1);
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        pre[0] = 0.0;
+        for (int t = 0; t < a.len; ++t) {
+            s += (double)row[t];
+            pre[t + 1] = s;
+        }
+    }
+    __syncthreads();
+    __shared__ double sh[256];
+    double best = -INFINITY;
+    for (int t = a.window + (int)threadIdx.x; t <= a.len; t += (int)blockDim.x) {
+        const double v = (pre[t] - pre[t - a.window]) / (double)a.window;
+        best = fmax(best, v);
+    }
+    sh[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.fmax[j] = sh[0];
+}
+
+// Thread = level: (1/N) sum_j exp(log_weight_j) [fmax_j >= a], j in order.
+__global__ void tail_probability_kernel(TailArgs a) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= a.n_levels) return;
+    const double lev = a.levels[q];
+    double s = 0.0;
+    for (int j = 0; j < a.n; ++j)
+        if (a.fmax[j] >= lev) s += exp(a.log_weight[j]);
+    a.prob[q] = s / (double)a.n;
+}
+
+hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(gktl_rebuild_kernel, dim3(a.n), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_window_max(const WindowMaxArgs& a, int rows, hipStream_t st) {
+    hipLaunchKernelGGL(window_max_kernel, dim3(rows), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_tail(const TailArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(tail_probability_kernel, dim3((a.n_levels + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,41 @@
+// Argument blocks of the estimator kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace lbm {
+
+constexpr int MAX_PERIODS = 4096;
+
+struct RebuildArgs {
+    const int* ancestors;     // [n_periods][n]
+    const double* integrals;  // [n_periods][n]  int A dt of each slot over each period
+    const double* ln_r;       // [n_periods]
+    const float* series;      // [n][ld] drag, period i at columns col0 + i*tau ...
+    int ld, col0, n, n_periods, tau;
+    double k;
+    float* traj;              // [n][n_periods*tau]
+    double* log_weight;       // [n]
+    double* traj_integral;    // [n]
+};
+
+struct WindowMaxArgs {
+    const float* series;  // [rows][len]
+    int len, window;
+    double* prefix;       // [rows][len+1] scratch
+    double* fmax;         // [rows]
+};
+
+struct TailArgs {
+    const double* fmax;
+    const double* log_weight;
+    const double* levels;
+    int n, n_levels;
+    double* prob;
+};
+
+hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st);
+hipError_t launch_window_max(const WindowMaxArgs& a, int rows, hipStream_t st);
+hipError_t launch_tail(const TailArgs& a, hipStream_t st);
+
+}  // namespace lbm

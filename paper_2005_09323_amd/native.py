@@ -68,6 +68,9 @@ _SIG = {
     "score_net_forward": (ctypes.c_int, [_P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "score_net_grad": (ctypes.c_int, [_P, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
     "score_net_adam": (ctypes.c_int, [_P, _P, _P, _P, _I, _D, _D, _D, _D, _P]),
+    "gktl_rebuild": (ctypes.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _D, _P, _P, _P, _P]),
+    "window_mean_max": (ctypes.c_int, [_P, _I, _I, _I, _P, _P, _P]),
+    "tail_probability": (ctypes.c_int, [_P, _P, _I, _P, _I, _P, _P]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -93,7 +96,7 @@ def declared_functions() -> list:
     """Names of the functions ``include/lbm.h`` declares."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_\w+|gktl_\w+|ams_\w+|score_\w+)\s*\(", text)) - {"lbm_ctx"})
+    return sorted(set(re.findall(r"\b(lbm_\w+|gktl_\w+|ams_\w+|score_\w+|window_mean_max|tail_probability)\s*\(", text)) - {"lbm_ctx"})
 
 
 def check(rc: int) -> None:

@@ -256,3 +256,70 @@ def test_window_mean_score_matches_oracle():
     ref = ogktl.window_means(series.astype(np.float64), 64)
     assert np.all(np.isneginf(gpu[:, :63]))
     assert np.allclose(gpu[:, 63:], ref[:, 63:], rtol=2e-7, atol=1e-7)
+
+
+def test_gktl_run_end_to_end_matches_oracle():
+    """A whole GKTL run on the LBM ensemble (device stepping, selection, cloning, lineage
+    rebuild, window maxima, reweighted tail probability) against the oracle's GKTL driving
+    the oracle LBM from the same seeded initial states."""
+    from paper_2005_09323_amd import rare
+    m = workloads.Member(64, 16, 0.6, 2e-5, (20, 5, 4))
+    ch = _channel(m)
+    n, tau, n_per, k, key, seed = 8, 16, 4, 0.5, 9, 31
+    mu, sigma, dt, window = 0.0, 1e-4, 1.0 / 16, 8
+    ens = _ens([m] * n, cap=n_per * tau + 1)
+    ens.init(seed, 1e-2)
+    ens.set_observable(mu, sigma, dt)
+    run = rare.run_gktl(ens, k, n_per, tau, key)
+    tr = rare.rebuild(run, ens)
+    fmax = rare.window_maxima(tr.series, window)
+
+    x0 = np.stack([olbm.collide(ch, olbm.init_populations(ch, olbm.init_density(ch, seed, i, 1e-2)))
+                   for i in range(n)])
+
+    def advance(x, period):
+        x = x.copy()
+        samples = np.empty((n, tau))
+        integ = np.empty(n)
+        for j in range(n):
+            fo = x[j]
+            for s in range(tau):
+                fo = olbm.collide(ch, olbm.stream(ch, fo))
+                samples[j, s] = olbm.drag(ch, fo)
+            x[j] = fo
+            integ[j] = math.fsum(((samples[j] - mu) / sigma * dt).tolist())
+        return x, samples, integ
+
+    res = ogktl.run(x0, advance, n_per, k, key)
+    assert np.array_equal(run.ancestors.cpu().numpy(), np.stack(res["ancestors"]))
+    assert np.allclose(run.ln_r.cpu().numpy(), res["ln_r"], rtol=1e-5, atol=1e-7)
+    ref_series = ogktl.reconstruct_series(res["samples"], res["ancestors"])
+    gpu_series = tr.series.double().cpu().numpy()
+    assert np.abs(gpu_series - ref_series).max() <= 1e-5 * np.abs(ref_series).max()
+    lin = ogktl.lineage(res["ancestors"])
+    ref_int = sum(res["integrals"][i][lin[:, i]] for i in range(n_per))
+    assert np.allclose(tr.integral.cpu().numpy(), ref_int, rtol=1e-5, atol=1e-6)
+    ref_lw = ogktl.unbias_log_weights(res["ln_r"], k, ref_int)
+    assert np.allclose(tr.log_weight.cpu().numpy(), ref_lw, rtol=1e-5, atol=1e-5)
+    ref_fmax = ogktl.window_mean_max(ref_series, window)
+    assert np.allclose(fmax.cpu().numpy(), ref_fmax, rtol=1e-5)
+    srt = np.unique(ref_fmax)
+    gap = 1e-3 * (np.abs(srt).max() + 1e-30)
+    # levels between distinct maxima and outside them: no ties with either side's rounding
+    levels = np.concatenate([[srt[0] - gap], 0.5 * (srt[1:] + srt[:-1]), [srt[-1] + gap]])
+    prob = rare.tail_probability(fmax, tr.log_weight, levels)
+    ref_prob = ogktl.tail_probability(ref_fmax, ref_lw, levels)
+    assert np.allclose(prob, ref_prob, rtol=1e-4)
+    assert abs(run.scgf(dt) - ogktl.scgf(res["ln_r"], n_per * tau * dt)) < 1e-5 * max(1.0, abs(run.scgf(dt)))
+
+
+def test_direct_sampling_estimator_matches_oracle():
+    from paper_2005_09323_amd import rare
+    series = workloads.score_series(6, 900, 21)
+    prob, r, fmax = rare.direct_return_times(torch.from_numpy(series).cuda(), 300, 50, [0.5, 1.0, 1.5])
+    blocks = series.astype(np.float64).reshape(18, 300)
+    ref_fmax = ogktl.window_mean_max(blocks, 50)
+    assert np.allclose(fmax.cpu().numpy(), ref_fmax, rtol=1e-6, atol=1e-7)
+    ref_prob = ogktl.tail_probability(ref_fmax, np.zeros(18), np.array([0.5, 1.0, 1.5]))
+    assert np.allclose(prob, ref_prob)
+    assert np.allclose(r, ogktl.return_time(ref_prob, 300, 50))
