@@ -212,8 +212,9 @@ int lbm_copy_state_in(lbm_ctx* ctx, int32_t m, const float* src_dev, int32_t t);
 /*
  * Trajectory-AMS selection (paper Section 4.1; Appendix B.1).  Independent of
  * any context: works on N score series of length t_len (device float[N][t_len],
- * row-major).  The maximum of each row (rows holding a non-finite value count
- * as -inf) goes to maxima_dev (device float[N]).  The level is the n_kill-th
+ * row-major).  The maximum of each row goes to maxima_dev (device float[N]);
+ * a row holding NaN or +inf (a blown-up trajectory) counts as -inf, while -inf
+ * entries are ordinary lowest scores (e.g. before a time average is defined).  The level is the n_kill-th
  * lowest maximum; every member at or below it is killed (ties together), in
  * increasing slot order, into killed_dev[0..K-1].  Kill j picks its parent
  * uniformly among the survivors (increasing slot order) with index
@@ -273,6 +274,17 @@ int window_mean_max(const float* series_dev, int32_t rows, int32_t len, int32_t 
  */
 int tail_probability(const double* fmax_dev, const double* log_weight_dev, int32_t n,
                      const double* levels_dev, int32_t n_levels, double* prob_dev, void* hip_stream);
+
+/*
+ * AMS score built from a learned prediction ghat for the target event
+ * {max_t F_T(t) >= level} (F_T: time-averaged drag): out = level where
+ * ft >= level, else min(ghat, the float just below level) (-inf for a
+ * non-finite ghat).  Then max_t out >= level exactly when the event happened,
+ * which keeps the AMS estimate of its probability unbiased whatever the
+ * prediction.  All arrays device float[count]; level finite and non-zero.
+ */
+int ams_clamped_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level, float* out_dev,
+                      void* hip_stream);
 
 /*
  * Learned AMS score (the paper's conclusion proposes learning the score

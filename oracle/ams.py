@@ -8,8 +8,8 @@ its maximum Q over [0, T_a].  One iteration (Appendix B.1):
 * level: the n_kill-th lowest maximum; every trajectory whose maximum is at
   or below it is discarded (ties go together), so K_j >= n_kill.  The paper
   discards one per iteration in its OU example and "the trajectories with the
-  lowest maxima" in the drag runs; n_kill covers both.  A non-finite score
-  counts as -inf.  If every trajectory is at the level the run is extinct.
+  lowest maxima" in the drag runs; n_kill covers both.  A trajectory whose
+  score series holds NaN or +inf (blown up) counts as -inf.  If every trajectory is at the level the run is extinct.
 * branching: each discarded slot picks a parent uniformly among the
   survivors (AMSP Philox stream at (kill index, iteration)), copies it up to
   its first time t_b with xi(t_b) > level (strictly above, so the copy
@@ -44,12 +44,14 @@ class KillBranch:
 
 
 def clean_maxima(series: np.ndarray) -> np.ndarray:
-    """Maximum of each row; rows holding a non-finite value count as -inf."""
+    """Maximum of each row.  A row holding NaN or +inf (a blown-up trajectory)
+    counts as -inf; -inf entries are ordinary lowest scores (no score yet)."""
     series = np.asarray(series, dtype=np.float64)
     out = np.empty(series.shape[0])
     for n in range(series.shape[0]):
         row = series[n]
-        out[n] = -math.inf if not np.all(np.isfinite(row)) else float(row.max())
+        bad = np.isnan(row).any() or np.isposinf(row).any()
+        out[n] = -math.inf if bad else float(row.max())
     return out
 
 

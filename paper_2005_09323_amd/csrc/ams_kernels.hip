@@ -8,7 +8,8 @@
 
 namespace lbm {
 
-// One block per member: max of the row, -inf if the row holds a non-finite value.
+// One block per member: max of the row; -inf if the row holds NaN or +inf (a
+// blown-up trajectory).  -inf entries are ordinary lowest scores.
 __global__ __launch_bounds__(256) void ams_maxima_kernel(const float* series, int t_len, float* maxima) {
     const int m = (int)blockIdx.x;
     const float* row = series + (long long)m * t_len;
@@ -18,7 +19,7 @@ __global__ __launch_bounds__(256) void ams_maxima_kernel(const float* series, in
     int bad = 0;
     for (int t = (int)threadIdx.x; t < t_len; t += 256) {
         const float v = row[t];
-        if (!isfinite(v)) bad = 1; else mx = fmaxf(mx, v);
+        if (isnan(v) || v == INFINITY) bad = 1; else mx = fmaxf(mx, v);
     }
     smax[threadIdx.x] = mx;
     sbad[threadIdx.x] = bad;

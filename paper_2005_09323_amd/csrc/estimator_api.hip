@@ -1,6 +1,8 @@
 // C-ABI entry points of the GKTL / direct-sampling estimators.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "../../include/lbm.h"
 #include "api_internal.hpp"
 #include "estimators.hpp"
@@ -62,4 +64,14 @@ extern "C" int tail_probability(const double* fmax_dev, const double* log_weight
     a.prob = prob_dev;
     hipError_t e = launch_tail(a, (hipStream_t)hip_stream);
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "tail probability");
+}
+
+extern "C" int ams_clamped_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level,
+                                 float* out_dev, void* hip_stream) {
+    if (!ghat_dev || !ft_dev || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (count < 0) return lbm_fail(LBM_EINVAL, "negative count");
+    if (!std::isfinite(level) || level == 0.0f) return lbm_fail(LBM_EINVAL, "level must be finite and non-zero");
+    if (count == 0) return LBM_OK;
+    hipError_t e = launch_clamped_score(ghat_dev, ft_dev, count, level, out_dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "clamped score");
 }

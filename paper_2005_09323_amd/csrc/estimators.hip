@@ -77,6 +77,25 @@ __global__ void tail_probability_kernel(TailArgs a) {
     a.prob[q] = s / (double)a.n;
 }
 
+// AMS score from a learned predictor, kept consistent with the target event
+// {max_t F_T(t) >= a}: the score is a once the time-averaged drag has reached
+// a, and the prediction held strictly below a before that, so that
+// max_t score >= a exactly when the event happened.
+__global__ void clamped_score_kernel(const float* ghat, const float* ft, long long count, float a, float* out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float below = __int_as_float(__float_as_int(a) - (a > 0.0f ? 1 : -1));  // next float under a
+    const float g = ghat[i];
+    out[i] = ft[i] >= a ? a : (isfinite(g) ? fminf(g, below) : -INFINITY);
+}
+
+hipError_t launch_clamped_score(const float* ghat, const float* ft, long long count, float a, float* out,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(clamped_score_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, ghat, ft,
+                       count, a, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(gktl_rebuild_kernel, dim3(a.n), dim3(256), 0, st, a);
     return hipGetLastError();

@@ -34,6 +34,8 @@ struct TailArgs {
     double* prob;
 };
 
+hipError_t launch_clamped_score(const float* ghat, const float* ft, long long count, float a, float* out,
+                                hipStream_t st);
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st);
 hipError_t launch_window_max(const WindowMaxArgs& a, int rows, hipStream_t st);
 hipError_t launch_tail(const TailArgs& a, hipStream_t st);

@@ -127,3 +127,158 @@ def direct_return_times(series: torch.Tensor, block: int, window: int, levels: S
     fmax = window_maxima(blocks, window)
     prob = tail_probability(fmax, torch.zeros_like(fmax), levels)
     return prob, return_time(prob, block, window), fmax
+
+
+# ---------------------------------------------------------------------------
+# trajectory AMS on the lattice-Boltzmann ensemble
+
+
+@dataclass
+class AmsResult:
+    n: int
+    k_history: List[int] = field(default_factory=list)
+    levels: List[float] = field(default_factory=list)
+    extinct: bool = False
+    member_steps: int = 0          # simulated member-steps, re-simulation and replay included
+    score_max: Optional[np.ndarray] = None   # final maxima of the score, per member
+    event_max: Optional[np.ndarray] = None   # final maxima of F_T on the score grid, per member
+
+    def probability(self, levels: Sequence[float]) -> np.ndarray:
+        """prod_j (1 - K_j / N) * (1/N) #{n : max F_T >= a} (unbiased AMS estimate)."""
+        f = 1.0
+        for kj in self.k_history:
+            f *= 1.0 - kj / self.n
+        q = np.asarray(self.event_max, dtype=np.float64)
+        return np.array([f * np.count_nonzero(q >= a) / self.n for a in levels])
+
+
+class AmsRunner:
+    """Trajectory AMS with branching from checkpoints (paper Section 4.1, Appendix B.1).
+
+    Every member runs t_a steps from its current state.  The score lives on a
+    grid of `stride` steps: the time-averaged drag F_T(t) over the last `window`
+    steps (plain) or, with a score network, the network's prediction clamped
+    for the target level (learned).  A killed member restarts from its parent's
+    last checkpoint before the branching time, replays the parent's dynamics
+    exactly (the kernels are deterministic) up to the branching time, is
+    perturbed there (Appendix D) and runs on to t_a.
+    """
+
+    def __init__(self, ens: Ensemble, t_a: int, window: int, stride: int, ckpt_every: int, key: int,
+                 eps: float, snapshots: torch.Tensor, net=None, feature_args: Optional[dict] = None,
+                 target: Optional[float] = None):
+        if t_a % ckpt_every or ckpt_every % stride:
+            raise ValueError("t_a must be a multiple of ckpt_every, itself a multiple of stride")
+        if net is not None and (feature_args is None or target is None):
+            raise ValueError("a learned score needs feature_args and the target level")
+        if ens.capacity < t_a + 1:
+            raise ValueError("the drag series needs t_a + 1 columns")
+        self.ens, self.t_a, self.window, self.stride, self.ckpt = ens, t_a, window, stride, ckpt_every
+        self.key, self.eps, self.snaps = key, eps, snapshots
+        self.net, self.fargs, self.target = net, feature_args, target
+        m = ens.members[0]
+        self.state_floats = 9 * m.nx * m.ny
+        n = ens.n
+        self.n_score = t_a // stride
+        self.ckpts = torch.empty((n, t_a // ckpt_every + 1, self.state_floats), dtype=torch.float32, device=ens.device)
+        self.ghat = torch.full((n, self.n_score), float("-inf"), dtype=torch.float32, device=ens.device)
+        self.time = np.zeros(n, dtype=np.int64)
+
+    # -- stepping ----------------------------------------------------------
+    def _features(self, members: Sequence[int], times: np.ndarray) -> None:
+        if self.net is None:
+            return
+        f = self.ens.features(0, self.ens.n, **self.fargs)
+        y = self.net.forward(f)
+        for m in members:
+            self.ghat[m, times[m] // self.stride - 1] = y[m]
+
+    def _advance(self, members: Sequence[int], perturb_at: dict, period: int) -> int:
+        """Run `members` from their times to t_a on the stride grid; returns member-steps."""
+        ens = self.ens
+        n = ens.n
+        active = [m for m in members if self.time[m] < self.t_a]
+        steps = 0
+        while active:
+            mask = np.zeros(n, dtype=np.int32)
+            mask[active] = 1
+            ens.set_active(mask.tolist())
+            ens.step(self.stride)
+            steps += self.stride * len(active)
+            self.time[active] += self.stride
+            self._features(active, self.time)  # before any perturbation: the child still equals its parent
+            pert = [m for m in active if perturb_at.get(m, -1) == self.time[m]]
+            if pert and self.eps != 0.0:
+                pmask = np.zeros(n, dtype=np.int32)
+                pmask[pert] = 1
+                ens.perturb(pmask.tolist(), self.key, period, self.eps, self.snaps)
+            for m in active:
+                if self.time[m] % self.ckpt == 0:
+                    ens.copy_state_out(m, self.ckpts[m, self.time[m] // self.ckpt])
+            active = [m for m in active if self.time[m] < self.t_a]
+        ens.set_active(None)
+        return steps
+
+    # -- scores ---------------------------------------------------------------
+    def event_series(self) -> torch.Tensor:
+        """F_T on the score grid: [N, t_a / stride] (-inf before the first full window)."""
+        ft = window_mean(self.ens.series[:, 1:self.t_a + 1].contiguous(), self.window)
+        return ft[:, self.stride - 1::self.stride].contiguous()
+
+    def score_series(self) -> torch.Tensor:
+        ft = self.event_series()
+        if self.net is None:
+            return ft
+        out = torch.empty_like(ft)
+        native.check(native.lib().ams_clamped_score(_ptr(self.ghat), _ptr(ft), ft.numel(), float(self.target),
+                                                    _ptr(out), _stream_handle(None)))
+        return out
+
+    # -- the algorithm --------------------------------------------------------
+    def run(self, n_kill: int, max_iter: int, threshold: float) -> AmsResult:
+        ens = self.ens
+        n = ens.n
+        res = AmsResult(n=n)
+        ens.set_time(1)
+        for m in range(n):
+            ens.copy_state_out(m, self.ckpts[m, 0])
+        self.time[:] = 0
+        res.member_steps += self._advance(range(n), {}, 0)
+        for it in range(max_iter):
+            score = self.score_series()
+            sel = ams_score_kill_branch(score, n_kill, self.key, it)
+            maxima = sel["maxima"].double().cpu().numpy()
+            if maxima.min() >= threshold:
+                break
+            if sel["parents"].numel() and int(sel["parents"][0].item()) < 0:
+                res.extinct = True
+                break
+            killed = sel["killed"].cpu().tolist()
+            parents = sel["parents"].cpu().tolist()
+            branch = sel["branch_t"].cpu().tolist()
+            res.k_history.append(len(killed))
+            res.levels.append(sel["level"])
+            perturb_at = {}
+            for k, p, tb in zip(killed, parents, branch):
+                t_b = (tb + 1) * self.stride              # score index -> trajectory time
+                c = t_b // self.ckpt
+                start = c * self.ckpt
+                ens.copy_state_in(k, self.ckpts[p, c], start + 1)
+                self.ckpts[k, :c + 1].copy_(self.ckpts[p, :c + 1])
+                ens.series[k, 1:start + 1].copy_(ens.series[p, 1:start + 1])
+                self.ghat[k, :start // self.stride].copy_(self.ghat[p, :start // self.stride])
+                self.time[k] = start
+                if start == t_b:
+                    # branching exactly on a checkpoint: perturb the restored state now
+                    mask = np.zeros(n, dtype=np.int32)
+                    mask[k] = 1
+                    if self.eps != 0.0:
+                        ens.perturb(mask.tolist(), self.key, it + 1, self.eps, self.snaps)
+                    ens.copy_state_out(k, self.ckpts[k, c])
+                else:
+                    perturb_at[k] = t_b
+            res.member_steps += self._advance(killed, perturb_at, it + 1)
+        score = self.score_series()
+        res.score_max = torch.max(score, dim=1).values.double().cpu().numpy()
+        res.event_max = torch.max(self.event_series(), dim=1).values.double().cpu().numpy()
+        return res

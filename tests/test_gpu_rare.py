@@ -323,3 +323,78 @@ def test_direct_sampling_estimator_matches_oracle():
     ref_prob = ogktl.tail_probability(ref_fmax, np.zeros(18), np.array([0.5, 1.0, 1.5]))
     assert np.allclose(prob, ref_prob)
     assert np.allclose(r, ogktl.return_time(ref_prob, 300, 50))
+
+
+def _ams_setup(n, t_a, stride, ckpt, eps, seed=17):
+    from paper_2005_09323_amd import rare
+    m = workloads.Member(64, 16, 0.6, 2e-5, (20, 5, 4))
+    ens = _ens([m] * n, cap=t_a + 1)
+    ens.init(seed, 1e-2)
+    snaps = workloads.snapshot_states(3, m, 5)
+    runner = rare.AmsRunner(ens, t_a, window=16, stride=stride, ckpt_every=ckpt, key=23, eps=eps,
+                            snapshots=torch.from_numpy(snaps).cuda())
+    return m, ens, snaps, runner
+
+
+def test_ams_branch_without_perturbation_replays_parent_exactly():
+    m, ens, _, runner = _ams_setup(6, 96, 8, 32, 0.0)
+    res = runner.run(n_kill=2, max_iter=3, threshold=1e9)
+    assert len(res.k_history) == 3
+    # with eps = 0 every branch is an exact copy of its parent: each final drag series
+    # equals some other member's, and the final maxima repeat
+    series = ens.series[:, 1:97].cpu().numpy()
+    uniq = {tuple(r.tolist()) for r in series}
+    assert len(uniq) < 6
+    assert res.member_steps > 6 * 96
+
+
+def test_ams_on_lbm_matches_oracle_ams():
+    """Device AMS (checkpoints, replay, perturbation, selection) vs the oracle's AMS re-simulating
+    with the oracle LBM from stored states."""
+    n, t_a, stride, ckpt, eps, n_kill, iters = 5, 96, 8, 32, 0.01, 1, 3
+    m, ens, snaps, runner = _ams_setup(n, t_a, stride, ckpt, eps)
+    res = runner.run(n_kill=n_kill, max_iter=iters, threshold=1e9)
+
+    ch = _channel(m)
+    fluid = ~olbm.solid_mask(ch)
+    snaps_full = np.stack([_full(snaps[q], ch) for q in range(3)])
+    states = []   # states[j][t]: post-collision state at trajectory time t
+    drags = []    # drags[j][t-1]: drag of step t
+    for j in range(n):
+        fo = olbm.collide(ch, olbm.init_populations(ch, olbm.init_density(ch, 17, j, 1e-2)))
+        st, dr = [fo], []
+        for _ in range(t_a):
+            fo = olbm.collide(ch, olbm.stream(ch, fo))
+            st.append(fo)
+            dr.append(olbm.drag(ch, fo))
+        states.append(st)
+        drags.append(dr)
+
+    def scores():
+        ft = ogktl.window_means(np.array(drags), 16)
+        return ft[:, stride - 1::stride]
+
+    k_hist = []
+    for it in range(iters):
+        kb = oams.kill_branch(scores(), n_kill, 23, it)
+        assert not kb.extinct
+        k_hist.append(len(kb.killed))
+        new_states, new_drags = list(states), list(drags)
+        for slot, parent, tb in zip(kb.killed, kb.parents, kb.branch_t):
+            t_b = (int(tb) + 1) * stride
+            st = list(states[parent][:t_b + 1])
+            dr = list(drags[parent][:t_b])
+            fo = opert.perturb(st[t_b], snaps_full, opert.alphas(23, int(slot), it + 1, 3), eps, fluid)
+            st[t_b] = fo
+            for _ in range(t_b, t_a):
+                fo = olbm.collide(ch, olbm.stream(ch, fo))
+                st.append(fo)
+                dr.append(olbm.drag(ch, fo))
+            new_states[slot], new_drags[slot] = st, dr
+        states, drags = new_states, new_drags
+    assert res.k_history == k_hist
+    ref_max = scores().max(axis=1)
+    assert np.allclose(res.event_max, ref_max, rtol=1e-4, atol=1e-8)
+    gpu_drag = ens.series[:, 1:t_a + 1].double().cpu().numpy()
+    ref_drag = np.array(drags)
+    assert np.abs(gpu_drag - ref_drag).max() <= 1e-4 * np.abs(ref_drag).max()

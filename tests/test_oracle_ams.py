@@ -72,3 +72,12 @@ def test_ams_unbiased_on_ou():
 def test_return_time_formula_limits():
     r = ams.return_time(np.array([0.0, 1e-9]), 5.0)
     assert r[0] == math.inf and math.isclose(r[1] * 1e-9 / 5.0, 1.0, rel_tol=1e-8)
+
+
+def test_minus_inf_entries_are_ordinary_scores():
+    series = np.array([[-np.inf, 0.5, 0.7], [-np.inf, -np.inf, 0.2], [np.inf, 0.1, 0.1], [0.3, np.nan, 0.0]])
+    q = ams.clean_maxima(series)
+    assert q.tolist() == [0.7, 0.2, -np.inf, -np.inf]
+    kb = ams.kill_branch(series, 3, 0, 0)
+    assert kb.level == 0.2 and kb.killed.tolist() == [1, 2, 3] and kb.parents.tolist() == [0, 0, 0]
+    assert kb.branch_t.tolist() == [1, 1, 1]
