@@ -1,0 +1,383 @@
+"""Return-time experiments on one GPU: GKTL, AMS with the plain and the learned
+score, and direct sampling, for extreme time-averaged drag.
+
+Protocol (paper Section 4.2.1 and its figure of return times): estimates are
+repeated on independent initial ensembles and their scatter (relative standard
+deviation over repeats) measures the error; the wall time a method needs for
+10 % relative error follows from the measured scatter with the usual 1/N
+scaling of the variance with the ensemble size.  Everything that computes runs
+in the library's kernels; this module orders the calls and reports.
+
+    python -m paper_2005_09323_amd.experiments all --out results/return_times.jsonl
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+from dataclasses import asdict, dataclass, field
+
+import numpy as np
+import torch
+
+from . import rare
+from .ensemble import Ensemble, ScoreNet, window_mean
+
+
+@dataclass
+class Flow:
+    """A numerically stable channel flow, statistically stationary after the burn-in, chaotic
+    enough that perturbed clones decorrelate within a few correlation times."""
+    nx: int = 512
+    ny: int = 128
+    tau: float = 0.505
+    force_x: float = 1e-6
+    square: tuple = (120, 56, 16)
+    u0: float = 0.02
+    burn: int = 200_000
+
+
+@dataclass
+class Member:
+    nx: int
+    ny: int
+    tau: float
+    force_x: float
+    square: tuple
+
+
+def _member(f: Flow) -> Member:
+    return Member(f.nx, f.ny, f.tau, f.force_x, f.square)
+
+
+def _sync_time() -> float:
+    torch.cuda.synchronize()
+    return time.perf_counter()
+
+
+def _progress(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _emit(out, rec: dict) -> None:
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if out:
+        with open(out, "a") as fh:
+            fh.write(line + "\n")
+
+
+def burn_in(flow: Flow, n: int, seed: int, cap: int) -> Ensemble:
+    """n members from independent seeded noise, run to the statistically stationary state."""
+    ens = Ensemble([_member(flow)] * n, series_capacity=cap)
+    ens.init(seed, 1e-3, ux0=flow.u0)
+    done = 0
+    while done < flow.burn:
+        chunk = min(cap - 2, flow.burn - done)
+        ens.set_time(1)
+        ens.step(chunk)
+        done += chunk
+        _progress(f"burn-in {n} members: {done}/{flow.burn} steps")
+    ens.set_time(1)
+    if int(ens.flags().sum().item()):
+        raise RuntimeError("a member blew up during burn-in")
+    return ens
+
+
+@dataclass
+class DragStats:
+    mu: float
+    sigma: float
+    tau_c: int          # steps to the first zero of the autocorrelation
+    sigma_window: dict = field(default_factory=dict)   # window -> std of the window mean
+
+
+def drag_stats(ens: Ensemble, steps: int, windows) -> DragStats:
+    """Run `steps` steps and measure the drag statistics (host FP64 analysis of the series)."""
+    ens.set_time(1)
+    ens.step(steps)
+    d = ens.drag(1, 1 + steps).double().cpu().numpy()
+    mu, sigma = float(d.mean()), float(d.std())
+    dd = d - d.mean(axis=1, keepdims=True)
+    acf = np.zeros(steps // 2)
+    for row in dd:
+        f = np.fft.rfft(row, 2 * steps)
+        acf += np.fft.irfft(f * np.conj(f))[: steps // 2]
+    acf /= acf[0]
+    tau_c = int(np.argmax(acf < 0)) if (acf < 0).any() else steps // 2
+    sw = {}
+    for w in windows:
+        c = np.cumsum(np.pad(d, ((0, 0), (1, 0))), axis=1)
+        means = (c[:, w:] - c[:, :-w]) / w
+        sw[w] = float(means.std())
+    ens.set_time(1)
+    return DragStats(mu, sigma, tau_c, sw)
+
+
+def _states_to(src: Ensemble, dst: Ensemble) -> None:
+    for m in range(dst.n):
+        dst.copy_state_in(m, src.state(m % src.n).contiguous(), 1)
+
+
+def _snapshots(src: Ensemble, n_snap: int) -> torch.Tensor:
+    return torch.stack([src.state(m).clone() for m in range(n_snap)]).contiguous()
+
+
+def _rel_scatter(values: np.ndarray) -> np.ndarray:
+    """Relative standard deviation over repeats (axis 0), per level; inf where undefined."""
+    v = np.asarray(values, dtype=np.float64)
+    out = np.full(v.shape[1], math.inf)
+    for q in range(v.shape[1]):
+        col = v[:, q]
+        if np.all(np.isfinite(col)) and col.mean() > 0:
+            out[q] = col.std(ddof=1) / col.mean()
+    return out
+
+
+def _distinct_roots(ancestors: torch.Tensor) -> int:
+    """Number of period-0 slots that still have a descendant at the end (lineage diversity)."""
+    anc = ancestors.cpu().numpy()
+    slot = np.arange(anc.shape[1])
+    for i in range(anc.shape[0] - 1, -1, -1):
+        slot = anc[i][slot]
+    return int(np.unique(slot).size)
+
+
+def gktl_and_direct(flow: Flow, n: int, repeats: int, ks, out=None, seed: int = 100,
+                    direct_steps: int = 200_000, eps: float = 0.002, clone_tc: float = 1.0,
+                    ta_windows: int = 2, n_src: int = 256):
+    """Direct-sampling reference from n_src stationary members, then GKTL repeats with n clones.
+
+    Each repeat starts from the source states 2 tau_c further on; when n > n_src the extra
+    members are perturbed copies, given 4 tau_c to separate before the run starts."""
+    n_src = min(n, n_src)
+    src = burn_in(flow, n_src, seed, cap=max(40_002, direct_steps + 2))
+    st = drag_stats(src, 20_000, windows=(512,))
+    tau = max(64, int(round(st.tau_c * clone_tc / 64)) * 64)  # cloning period in correlation times
+    window = max(1, round(5 * st.tau_c / tau)) * tau           # T ~ 5 tau_c, a multiple of tau
+    n_per = ta_windows * window // tau                         # T_a = ta_windows * T
+    t_a = n_per * tau
+    dt = 1.0 / st.tau_c                                        # time in correlation times
+    # direct reference from the source ensemble: long run cut into blocks of t_a
+    direct_len = direct_steps // t_a * t_a
+    t0 = _sync_time()
+    src.set_time(1)
+    src.step(direct_len)
+    direct_wall = _sync_time() - t0
+    _progress(f"direct run: {direct_len} steps x {n_src} members in {direct_wall:.1f} s")
+    series = src.drag(1, 1 + direct_len).contiguous()
+    d = series.double().cpu().numpy()
+    cs = np.cumsum(np.pad(d, ((0, 0), (1, 0))), axis=1)
+    means = (cs[:, window:] - cs[:, :-window]) / window
+    sig_t = float(means.std())
+    mu_t = float(means.mean())
+    levels = [mu_t + z * sig_t for z in (1.5, 2.0, 2.5, 3.0, 3.5, 4.0)]
+    p_dir, r_dir, _ = rare.direct_return_times(series, t_a, window, levels)
+    n_blocks = n_src * (direct_len // t_a)
+    step_cost = direct_wall / (n_src * direct_len)             # seconds per member-step
+    dir_wall10 = []
+    for p in p_dir:
+        nb = (1 - p) / (p * 0.01) if p > 0 else math.inf      # blocks for 10 % relative error
+        dir_wall10.append(nb * t_a * step_cost)
+    _emit(out, {"experiment": "direct", "flow": asdict(flow), "n": n_src, "mu": st.mu, "sigma": st.sigma,
+                "tau_c_steps": st.tau_c, "window_T": window, "t_a": t_a, "tau_clone": tau,
+                "mu_T": mu_t, "sigma_T": sig_t, "levels": levels, "blocks": n_blocks,
+                "p": p_dir.tolist(), "r_steps": r_dir.tolist(),
+                "rel_err_binomial": [math.sqrt((1 - p) / (n_blocks * p)) if p > 0 else None for p in p_dir],
+                "s_per_member_step": step_cost, "wall_s_to_10pct": dir_wall10})
+    snaps = _snapshots(src, 10)
+    g = Ensemble([_member(flow)] * n, series_capacity=t_a + 2)
+    extra = [1 if m >= n_src else 0 for m in range(n)]
+    for ki, k in enumerate(ks):
+        p_all, walls, lams, roots = [], [], [], []
+        for rep in range(repeats):
+            src.set_time(1)
+            src.step(2 * st.tau_c)                             # decorrelate the restarts
+            _states_to(src, g)
+            if n > n_src:
+                g.perturb(extra, 90_000 + 100 * ki + rep, 0, eps, snaps)
+                g.set_time(1)
+                g.step(4 * st.tau_c)
+            g.set_time(1)
+            g.set_observable(st.mu, st.sigma, dt)
+            g.accum.zero_()
+            t0 = _sync_time()
+            run = rare.run_gktl(g, k, n_per, tau, key=1000 * (ki + 1) + rep, eps=eps, snapshots=snaps)
+            walls.append(_sync_time() - t0)
+            roots.append(_distinct_roots(run.ancestors))
+            p, _, _, _ = rare.gktl_return_times(run, g, window, levels)
+            p_all.append(p)
+            lams.append(run.scgf(dt))
+            _progress(f"gktl k={k} repeat {rep}: {walls[-1]:.2f} s, roots {roots[-1]}")
+        p_all = np.array(p_all)
+        p_mean = p_all.mean(axis=0)
+        scat = np.array([p_all[:, q].std(ddof=1) / p_mean[q] if p_mean[q] > 0 else math.inf
+                         for q in range(len(levels))])
+        wall = float(np.mean(walls))
+        _emit(out, {"experiment": "gktl", "k": k, "n": n, "repeats": repeats, "t_a": t_a, "tau_clone": tau,
+                    "window_T": window, "levels": levels, "p_mean": p_mean.tolist(),
+                    "r_steps": rare.return_time(p_mean, t_a, window).tolist(),
+                    "p_rel_scatter": scat.tolist(),
+                    "direct_rel_err_equal_cost": [math.sqrt((1 - q) / (n * q)) if q > 0 else None for q in p_dir],
+                    "p_repeats": p_all.tolist(), "scgf_mean": float(np.mean(lams)),
+                    "eps": eps, "distinct_roots_mean": float(np.mean(roots)),
+                    "wall_s_per_run": wall,
+                    "wall_s_to_10pct": [wall * max(1.0, (s / 0.1) ** 2) if math.isfinite(s) else None
+                                        for s in scat]})
+    g.close()
+    src.close()
+
+
+def train_score(flow: Flow, n: int, rounds: int, horizon: int, out=None, seed: int = 7, epochs: int = 8):
+    """(snapshot, mean drag over the next `horizon` steps) pairs from the ensemble itself, then
+    Adam on the device network.  Returns (net, label mean, label std, feature args)."""
+    src = burn_in(flow, n, seed, cap=horizon + 2)
+    x0, y0, s = flow.square
+    fargs = dict(px0=x0 + s, py0=y0 + s // 2 - 32, patch=64, pool=4, u_scale=20.0, rho_scale=200.0)
+    feats, labels = [], []
+    for r in range(rounds):
+        if r % 20 == 0:
+            _progress(f"training pairs: round {r}/{rounds}")
+        feats.append(src.features(0, n, **fargs))
+        src.set_time(1)
+        src.step(horizon)
+        labels.append(window_mean(src.series[:, 1:horizon + 1].contiguous(), horizon)[:, -1].clone())
+    x = torch.cat(feats).contiguous()
+    ys = torch.cat(labels).contiguous()   # labels in drag units
+    mu, sd = float(ys.mean().item()), float(ys.std().item())
+    src.close()
+    n_tot = x.shape[0]
+    n_val = n_tot // 10
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(n_tot, generator=g).cuda()
+    val, tr = perm[:n_val], perm[n_val:]
+    # He-initialised weights, zero biases, read-out bias at the label mean
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape, fan in (("w1", (32, 3, 3, 3), 27), ("b1", (32,), 0), ("w2", (32, 32, 3, 3), 288),
+                             ("b2", (32,), 0), ("w3", (32, 32, 3, 3), 288), ("b3", (32,), 0),
+                             ("w4", (32,), 32), ("b4", (1,), 0)):
+        if name.startswith("w"):
+            parts.append(rng.standard_normal(shape).ravel() * math.sqrt(2.0 / fan) * (sd if name == "w4" else 1.0))
+        else:
+            parts.append(np.full(int(np.prod(shape)), mu if name == "b4" else 0.0))
+    flat = np.concatenate(parts).astype(np.float32)
+    net = ScoreNet(torch.from_numpy(flat), 256)
+    batch = 256
+    t0 = _sync_time()
+    steps = 0
+    for ep in range(epochs):
+        order = tr[torch.randperm(len(tr), generator=g).cuda()]
+        for b in range(0, len(order) - batch + 1, batch):
+            idx = order[b:b + batch]
+            net.train_step(x[idx].contiguous(), ys[idx].contiguous(), lr=3e-4)
+            steps += 1
+    train_wall = _sync_time() - t0
+    pv = torch.cat([net.forward(x[val[i:i + batch]].contiguous()) for i in range(0, n_val, batch)])
+    yv = ys[val]
+    r2 = 1.0 - float(((pv - yv) ** 2).mean().item()) / float(yv.var().item())
+    _emit(out, {"experiment": "score_training", "samples": n_tot, "horizon": horizon, "epochs": epochs,
+                "adam_steps": steps, "train_wall_s": train_wall, "validation_r2": r2,
+                "label_mean": mu, "label_std": sd})
+    return net, mu, sd, fargs
+
+
+def ams_compare(flow: Flow, n: int, repeats: int, out=None, seed: int = 200, window: int = 512,
+                rounds: int = 200, n_kill_frac: float = 1 / 16, max_iter: int = 400, eps: float = 0.002,
+                z: float = 5.0, direct_steps: int = 200_000):
+    """AMS with the plain score (the running window mean of the drag) and with the learned score,
+    for the event max over [0, T_a] of the `window`-step mean drag >= mu + z sigma_window.  Each run
+    stops once every trajectory has reached that level, so the estimate is for that level only."""
+    net, lab_mu, lab_sd, fargs = train_score(flow, n, rounds, window, out=out)
+    src = burn_in(flow, n, seed, cap=max(40_002, direct_steps + 2))
+    t0 = _sync_time()
+    st = drag_stats(src, 20_000, windows=(window,))
+    step_cost = (_sync_time() - t0) / (n * 20_000)             # seconds per member-step
+    t_a = max(5 * st.tau_c // 512, 2) * 512
+    level = float(np.float32(st.mu + z * st.sigma_window[window]))   # the FP32 level the scores see
+    # direct-sampling reference on the same event: blocks of t_a steps of the stationary source
+    direct_len = direct_steps // t_a * t_a
+    src.set_time(1)
+    src.step(direct_len)
+    n_blocks = n * (direct_len // t_a)
+    blocks = src.drag(1, 1 + direct_len).reshape(n_blocks, t_a).contiguous()
+    stride = 32                                                # the AMS score grid
+    fmax = window_mean(blocks, window)[:, stride - 1::stride].max(dim=1).values
+    p_dir = float((fmax >= level).double().mean().item())
+    del blocks, fmax
+    _emit(out, {"experiment": "ams_direct_reference", "n": n, "t_a": t_a, "window_T": window, "level": level,
+                "level_sigma_window": z, "blocks": n_blocks, "p": p_dir,
+                "rel_err_binomial": math.sqrt((1 - p_dir) / (n_blocks * p_dir)) if p_dir > 0 else None,
+                "s_per_member_step": step_cost})
+    snaps = _snapshots(src, 10)
+    for name, use_net in (("plain", None), ("learned", net)):
+        probs, walls, costs, iters, extinct = [], [], [], [], 0
+        ens = Ensemble([_member(flow)] * n, series_capacity=t_a + 2)
+        for rep in range(repeats):
+            src.set_time(1)
+            src.step(2 * st.tau_c)
+            _states_to(src, ens)
+            runner = rare.AmsRunner(ens, t_a, window, stride=32, ckpt_every=512, key=3000 + rep, eps=eps,
+                                    snapshots=snaps, net=use_net, feature_args=fargs if use_net else None,
+                                    target=level if use_net else None)
+            t0 = _sync_time()
+            res = runner.run(n_kill=max(1, int(n * n_kill_frac)), max_iter=max_iter, threshold=level)
+            walls.append(_sync_time() - t0)
+            costs.append(res.member_steps)
+            iters.append(len(res.k_history))
+            extinct += int(res.extinct)
+            probs.append(0.0 if res.extinct else res.probability([level])[0])
+            _progress(f"ams {name} repeat {rep}: {walls[-1]:.2f} s, {iters[-1]} iterations, p={probs[-1]:.4g}")
+            del runner
+            torch.cuda.empty_cache()
+        probs = np.array(probs)
+        p_mean = float(probs.mean())
+        rel = float(probs.std(ddof=1) / p_mean) if p_mean > 0 else math.inf
+        wall = float(np.mean(walls))
+        cost = float(np.mean(costs))
+        n_eq = cost / t_a                                      # direct trajectories of the same cost
+        _emit(out, {"experiment": "ams", "score": name, "n": n, "repeats": repeats, "t_a": t_a,
+                    "window_T": window, "level": level, "level_sigma_window": z, "p_mean": p_mean,
+                    "p_rel_scatter": rel, "p_repeats": probs.tolist(), "iterations_mean": float(np.mean(iters)),
+                    "extinct_runs": extinct, "p_direct": p_dir,
+                    "r_steps": float(-t_a / math.log1p(-p_mean)) if p_mean > 0 else None,
+                    "member_steps_mean": cost, "wall_s_per_run": wall,
+                    "wall_s_to_10pct": wall * max(1.0, (rel / 0.1) ** 2) if math.isfinite(rel) else None,
+                    "direct_rel_err_equal_cost": math.sqrt((1 - p_mean) / (n_eq * p_mean)) if p_mean > 0 else None,
+                    "direct_wall_s_to_10pct": (1 - p_mean) / (p_mean * 0.01) * t_a * step_cost
+                    if p_mean > 0 else None})
+        ens.close()
+    src.close()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["gktl", "ams", "all"])
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--repeats", type=int, default=10)
+    ap.add_argument("--burn", type=int, default=Flow.burn)
+    ap.add_argument("--rounds", type=int, default=200)
+    ap.add_argument("--ams-n", type=int, default=256)
+    ap.add_argument("--ams-z", type=float, default=5.0, help="AMS level in window standard deviations")
+    ap.add_argument("--direct-steps", type=int, default=200_000)
+    ap.add_argument("--eps", type=float, default=0.002)
+    ap.add_argument("--clone-tc", type=float, default=1.0, help="GKTL cloning period in correlation times")
+    ap.add_argument("--ta-windows", type=int, default=2, help="GKTL trajectory length T_a in windows T")
+    ap.add_argument("--ks", default="0.25,0.5,1")
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    flow = Flow(burn=args.burn)
+    if args.which in ("gktl", "all"):
+        gktl_and_direct(flow, args.n, args.repeats, ks=[float(k) for k in args.ks.split(",")],
+                        out=args.out, direct_steps=args.direct_steps, eps=args.eps, clone_tc=args.clone_tc,
+                        ta_windows=args.ta_windows)
+    if args.which in ("ams", "all"):
+        ams_compare(flow, args.ams_n, args.repeats, out=args.out, rounds=args.rounds, eps=args.eps,
+                    z=args.ams_z, direct_steps=args.direct_steps)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

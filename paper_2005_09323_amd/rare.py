@@ -144,7 +144,9 @@ class AmsResult:
     event_max: Optional[np.ndarray] = None   # final maxima of F_T on the score grid, per member
 
     def probability(self, levels: Sequence[float]) -> np.ndarray:
-        """prod_j (1 - K_j / N) * (1/N) #{n : max F_T >= a} (unbiased AMS estimate)."""
+        """prod_j (1 - K_j / N) * (1/N) #{n : max F_T >= a}: the unbiased AMS estimate for levels at
+        or above the one every trajectory reached when the run stopped (below it, the final ensemble
+        no longer holds the trajectories that were discarded on the way)."""
         f = 1.0
         for kj in self.k_history:
             f *= 1.0 - kj / self.n
@@ -175,7 +177,10 @@ class AmsRunner:
             raise ValueError("the drag series needs t_a + 1 columns")
         self.ens, self.t_a, self.window, self.stride, self.ckpt = ens, t_a, window, stride, ckpt_every
         self.key, self.eps, self.snaps = key, eps, snapshots
-        self.net, self.fargs, self.target = net, feature_args, target
+        # scores are FP32: the clamp level and the stopping level are taken at FP32 so that a
+        # trajectory whose score reached the level also compares as having reached it here
+        self.net, self.fargs = net, feature_args
+        self.target = None if target is None else float(np.float32(target))
         m = ens.members[0]
         self.state_floats = 9 * m.nx * m.ny
         n = ens.n
@@ -236,6 +241,7 @@ class AmsRunner:
 
     # -- the algorithm --------------------------------------------------------
     def run(self, n_kill: int, max_iter: int, threshold: float) -> AmsResult:
+        threshold = float(np.float32(threshold))
         ens = self.ens
         n = ens.n
         res = AmsResult(n=n)
