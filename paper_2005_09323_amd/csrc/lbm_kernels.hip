@@ -11,15 +11,21 @@
 namespace lbm {
 
 // BGK relaxation with Guo forcing of one cell, in deviation form:
-//   rho = 1 + sum d_i,  j = sum c_i d_i,  u = (j + F/2) / rho,
-//   d_i^eq = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)],
-//   d_i <- d_i + omega (d_i^eq - d_i) + w_i (1 - omega/2) [3 (c_ix - u_x) + 9 (c.u) c_ix] F.
+//   rho = 1 + sum d_i,  J = sum c_i d_i + F/2 = rho u,
+//   d_i^eq = w_i [(rho - 1) + 3 c.J + 4.5 (c.J)(c.u) - 1.5 J.u],
+//   d_i <- (1 - omega) d_i + omega d_i^eq + w_i (1 - omega/2) [3 (c_ix - u_x) + 9 (c.u) c_ix] F.
 // (The w_i of f_i = w_i + d_i cancel exactly between f_i and f_i^eq.)
+// Opposite directions i and i' (c_i' = -c_i) share the even part of that
+// update and differ in the sign of the odd part, so each pair costs one
+// even and one odd term:
+//   even = b + 4.5 omega (c.J)(c.u) + g9 c_ix (c.u) c_ix,  odd = 3 omega c.J + g3 c_ix,
+//   b = omega ((rho - 1) - 1.5 J.u) - g3 u_x,  g3 = 3 (1 - omega/2) F,  g9 = 9 (1 - omega/2) F,
+//   d_i <- (1 - omega) d_i + w_i (even + odd),  d_i' <- (1 - omega) d_i' + w_i (even - odd).
 // The populations are stored in FP32 but the update is computed in FP64:
 // the flow changes little from one step to the next, so FP32 rounding in
 // the update repeats with the same sign step after step and its error grows
 // linearly in time, while one rounding on store does not.  The update is
-// done in place, one direction at a time, to keep few doubles live.
+// done in place, one pair at a time, to keep few doubles live.
 //
 // links: bit i set when x + c_i lies in the square; returns the momentum
 // those links hand to the square, sum of 2 c_ix f_i^out (the w_i parts
@@ -28,7 +34,7 @@ __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsign
     const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
     const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
     const double drho = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;
-    const double jx = ((d1 - d3) + (d5 - d6)) + (d8 - d7);
+    const double jx = (((d1 - d3) + (d5 - d6)) + (d8 - d7)) + m.half_fx;
     const double jy = ((d2 - d4) + (d5 - d7)) + (d6 - d8);
     const double rho = 1.0 + drho;
     // 1/rho: hardware FP32 reciprocal refined by two Newton steps in FP64
@@ -36,21 +42,31 @@ __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsign
     double inv = (double)__builtin_amdgcn_rcpf((float)rho);
     inv = inv * (2.0 - rho * inv);
     inv = inv * (2.0 - rho * inv);
-    const double ux = (jx + m.half_fx) * inv;
+    const double ux = jx * inv;
     const double uy = jy * inv;
-    const double usq = 1.5 * (ux * ux + uy * uy);
     const double om = m.omega;
+    const double keep = 1.0 - om;
+    const double c3 = 3.0 * om, c45 = 4.5 * om;
+    const double b = om * (drho - 1.5 * (jx * ux + jy * uy)) - m.gf3 * ux;
     double drag = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const double di = (double)d[i];
-        const double cu = (double)CX[i] * ux + (double)CY[i] * uy;
-        const double deq = WD[i] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq));
-        const double src = WD[i] * (m.gf3 * ((double)CX[i] - ux) + m.gf9 * cu * (double)CX[i]);
-        const double out = di + om * (deq - di) + src;
-        if (CX[i] != 0 && (links >> i) & 1u) drag += 2.0 * (double)CX[i] * out;
-        d[i] = (float)out;
-    }
+    d[0] = (float)(keep * d0 + WD[0] * b);
+    // pair (ip, im) with c_ip = -c_im; e = c_ip.J, v = c_ip.u; xmove: c_ip,x = +1 (else 0)
+    auto pair = [&](int ip, int im, double dp, double dm, double e, double v, bool xmove) {
+        const double even = xmove ? fma(c45 * e, v, fma(m.gf9, v, b)) : fma(c45 * e, v, b);
+        const double odd = xmove ? fma(c3, e, m.gf3) : c3 * e;
+        const double op = fma(keep, dp, WD[ip] * (even + odd));
+        const double on = fma(keep, dm, WD[im] * (even - odd));
+        if (xmove) {
+            if ((links >> ip) & 1u) drag += 2.0 * op;
+            if ((links >> im) & 1u) drag -= 2.0 * on;
+        }
+        d[ip] = (float)op;
+        d[im] = (float)on;
+    };
+    pair(1, 3, d1, d3, jx, ux, true);
+    pair(2, 4, d2, d4, jy, uy, false);
+    pair(5, 7, d5, d7, jx + jy, ux + uy, true);
+    pair(8, 6, d8, d6, jx - jy, ux - uy, true);
     return drag;
 }
 
@@ -233,8 +249,10 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 // Fused pull-stream + collide step over the whole ensemble.  Workgroup =
 // TYT waves; a tile is 256 columns by TYT*R rows; wave w handles rows
 // w, w + TYT, ... of the tile.
+// One-row shapes are held to 96 VGPRs (5 waves per SIMD): the memory-bound
+// step needs the waves in flight more than the registers.
 template <int TYT, int R>
-__global__ __launch_bounds__(64 * TYT) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4))) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec;
     const int mi = block_to_member(a, b, tx, ty, vec);
