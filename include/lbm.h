@@ -156,11 +156,20 @@ int lbm_set_time(lbm_ctx* ctx, int32_t t);
 int lbm_flags(const lbm_ctx* ctx, int32_t* out_dev);
 
 /*
- * Tile shape of the step kernel (an index into the library's table of
- * shapes; see lbm_tile_count).  Every shape computes bit-identical results.
+ * Launch shape of the lattice step (an index into the library's table of
+ * shapes; see lbm_tile_count).  Every shape computes bit-identical states and
+ * drag.  Shapes 0-15 make one step per launch (tiles of 256 columns by a few
+ * rows).  Shapes 16-19 make two steps per launch: a workgroup sweeps a strip
+ * of 256 columns from the bottom row to the top and keeps the intermediate
+ * step in on-chip memory, so the populations cross HBM once per two steps.
+ * They apply when every member's width is a multiple of 256; otherwise, and
+ * for the last step of an odd batch, the library steps with shape 0.  The
+ * default is shape 16.
  */
 int lbm_set_tile(lbm_ctx* ctx, int32_t tile_id);
 int32_t lbm_tile_count(void);
+/* Lattice steps per launch of the shape in use on this ensemble (1 or 2). */
+int lbm_launch_steps(const lbm_ctx* ctx, int32_t* steps);
 /* Time every tile shape on this ensemble (n_steps each, on the context's
    stream, synchronising it) and keep the fastest.  Writes the chosen id. */
 int lbm_autotune(lbm_ctx* ctx, int32_t n_steps, int32_t* best_tile);

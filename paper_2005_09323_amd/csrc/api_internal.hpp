@@ -11,7 +11,7 @@
 namespace lbm {
 
 constexpr int MAX_MEMBERS = 4096;
-constexpr int DEFAULT_TILE = 0;
+constexpr int DEFAULT_TILE = 16;  // two steps per launch (falls back to shape 0 where it does not apply)
 
 struct MaskBits {
     unsigned w[MAX_MEMBERS / 32];
@@ -60,9 +60,16 @@ struct lbm_ctx {
     int chunk = 64;
     double mu = 0.0, sigma = 1.0, dt = 1.0;
     int tile_id = lbm::DEFAULT_TILE;
+    // one-step launches: the tile shape in use (shape 0 when a two-step shape is chosen)
+    int one_tile = 0;
     int nseg = 0;
     int total_blocks = 0;
     lbm::Segment seg[lbm::MAX_SEGMENTS];
+    // two-step launches (when the chosen shape has two steps and every member qualifies)
+    bool two_step = false;
+    int nseg2 = 0;
+    int total_blocks2 = 0;
+    lbm::Segment seg2[lbm::MAX_SEGMENTS];
     RareScratch rare;
 };
 

@@ -54,21 +54,25 @@ struct FinalizeArgs {
     long long ld;        // row stride of the drag series
     int n;               // steps in this chunk
     int accumulate;      // add the observable to accum (0 for step 0)
-    int advance_parity;  // 1: the chunk's steps ping-ponged the buffers; 0 for step 0
+    int swap_parity;     // parity of the number of buffer swaps in this chunk (one per kernel launch)
     double mu;
     double inv_sigma_dt; // dt / sigma
 };
 
 struct TileShape {
-    int tyt;  // waves per workgroup
-    int r;    // rows per wave (a tile is 256 columns by tyt * r rows)
-    int xcd;  // 1: remap workgroups so each XCD gets a contiguous range of tiles
+    int tyt;    // waves per workgroup
+    int r;      // rows per wave (a tile is 256 columns by tyt * r rows); 1 for two-step shapes
+    int xcd;    // 1: remap workgroups so each XCD gets a contiguous range of tiles
+    int steps;  // lattice steps per launch: 1, or 2 (a strip of 256 columns swept bottom to top)
 };
 
 extern const TileShape TILE_SHAPES[];
 extern const int N_TILE_SHAPES;
 
 hipError_t launch_step(int tile_id, const StepArgs& a, hipStream_t st);
+// two steps per launch, `waves` rows per iteration; the segment table must
+// describe strips of 256 columns (tiles_per_member = tiles_x = nx / 256)
+hipError_t launch_step2(int waves, const StepArgs& a, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, int n_members, long long max_cells, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs& a, int n_members, hipStream_t st);
 

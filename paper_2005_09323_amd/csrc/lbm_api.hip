@@ -98,20 +98,20 @@ static int validate_member(const lbm_member_desc& d, int i) {
     return LBM_OK;
 }
 
-// Build the segment table of the current tile shape: runs of consecutive
-// members with the same lattice shape share a tiling.
-static int build_segments(lbm_ctx* c) {
-    const TileShape ts = TILE_SHAPES[c->tile_id];
+// Segment table of one tiling: runs of consecutive members with the same
+// lattice shape share it.  strips: the two-step kernel's tiling (one
+// workgroup per 256-column strip, all rows).
+static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* seg, int& nseg, int& total) {
     const int rows = ts.tyt * ts.r;
-    c->nseg = 0;
+    nseg = 0;
     int blocks = 0;
     for (int m = 0; m < c->n; ++m) {
         const auto& d = c->desc[m];
-        const bool same = c->nseg > 0 && c->desc[c->seg[c->nseg - 1].member_begin].nx == d.nx &&
-                          c->desc[c->seg[c->nseg - 1].member_begin].ny == d.ny;
-        const int tx = (d.nx + 255) / 256, ty = (d.ny + rows - 1) / rows;
+        const bool same = nseg > 0 && c->desc[seg[nseg - 1].member_begin].nx == d.nx &&
+                          c->desc[seg[nseg - 1].member_begin].ny == d.ny;
+        const int tx = (d.nx + 255) / 256, ty = strips ? 1 : (d.ny + rows - 1) / rows;
         if (!same) {
-            if (c->nseg == MAX_SEGMENTS)
+            if (nseg == MAX_SEGMENTS)
                 return lbm_fail(LBM_EUNSUPPORTED, "more than %d runs of distinct lattice shapes; group members by shape",
                                 MAX_SEGMENTS);
             Segment s;
@@ -122,14 +122,36 @@ static int build_segments(lbm_ctx* c) {
             // four cells per lane needs 16-byte rows, and 32-bit byte offsets over the member's block
             s.vec = (d.nx % 4 == 0 && 36LL * d.nx * d.ny < (1LL << 31)) ? 1 : 0;
             s.pad_ = 0;
-            c->seg[c->nseg++] = s;
+            seg[nseg++] = s;
         }
         if ((long long)blocks + (long long)tx * ty > (1LL << 31) - 1)
             return lbm_fail(LBM_EUNSUPPORTED, "ensemble needs more than 2^31 workgroups");
         blocks += tx * ty;
     }
-    c->total_blocks = blocks;
+    total = blocks;
     return LBM_OK;
+}
+
+// Tables of the current tile shape.  A two-step shape applies when every
+// member's width is a multiple of 256 and its block fits 32-bit byte
+// offsets; otherwise (and for the last step of an odd chunk) the library
+// steps with the one-step shape 0, which gives the same results.
+static int build_segments(lbm_ctx* c) {
+    const TileShape ts = TILE_SHAPES[c->tile_id];
+    c->two_step = false;
+    c->one_tile = c->tile_id;
+    if (ts.steps == 2) {
+        c->one_tile = 0;
+        bool ok = true;
+        for (int m = 0; m < c->n; ++m)
+            ok = ok && c->desc[m].nx % 256 == 0 && 36LL * c->desc[m].nx * c->desc[m].ny < (1LL << 31);
+        if (ok) {
+            int rc = build_table(c, ts, true, c->seg2, c->nseg2, c->total_blocks2);
+            if (rc) return rc;
+            c->two_step = true;
+        }
+    }
+    return build_table(c, TILE_SHAPES[c->one_tile], false, c->seg, c->nseg, c->total_blocks);
 }
 
 extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t n_members, float* pop_a,
@@ -240,7 +262,7 @@ extern "C" int lbm_destroy(lbm_ctx* c) {
     return LBM_OK;
 }
 
-static FinalizeArgs finalize_args(lbm_ctx* c, int n, int accumulate, int advance) {
+static FinalizeArgs finalize_args(lbm_ctx* c, int n, int accumulate, int swap_parity) {
     FinalizeArgs f;
     f.members = c->d_members;
     f.active = c->d_active;
@@ -253,7 +275,7 @@ static FinalizeArgs finalize_args(lbm_ctx* c, int n, int accumulate, int advance
     f.ld = c->cap;
     f.n = n;
     f.accumulate = accumulate;
-    f.advance_parity = advance;
+    f.swap_parity = swap_parity;
     f.mu = c->mu;
     f.inv_sigma_dt = c->dt / c->sigma;
     return f;
@@ -326,24 +348,40 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
     a.pop0 = c->pop[0];
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
-    a.xcd = TILE_SHAPES[c->tile_id].xcd;
+    a.xcd = TILE_SHAPES[c->one_tile].xcd;
     a.total_blocks = c->total_blocks;
     a.nseg = c->nseg;
     for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
+    StepArgs a2 = a;
+    if (c->two_step) {
+        a2.xcd = TILE_SHAPES[c->tile_id].xcd;
+        a2.total_blocks = c->total_blocks2;
+        a2.nseg = c->nseg2;
+        for (int s = 0; s < c->nseg2; ++s) a2.seg[s] = c->seg2[s];
+    }
+    const int waves2 = TILE_SHAPES[c->tile_id].tyt;
     hipError_t e;
     int done = 0;
     while (done < n_steps) {
         const int chunk = std::min(n_steps - done, c->chunk);
-        for (int s = 0; s < chunk; ++s) {
+        // every launch swaps the buffers once, whether it makes one step or two
+        int launches = 0, s = 0;
+        if (c->two_step)
+            for (; s + 1 < chunk; s += 2, ++launches) {
+                a2.slot = s;
+                a2.flip = launches & 1;
+                if ((e = launch_step2(waves2, a2, c->stream)) != hipSuccess) return lbm_hip_fail(e, "two-step kernel");
+            }
+        for (; s < chunk; ++s, ++launches) {
             a.slot = s;
-            a.flip = s & 1;
-            if ((e = launch_step(c->tile_id, a, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
+            a.flip = launches & 1;
+            if ((e = launch_step(c->one_tile, a, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
         }
-        if ((e = launch_finalize(finalize_args(c, chunk, 1, 1), c->n, c->stream)) != hipSuccess)
+        if ((e = launch_finalize(finalize_args(c, chunk, 1, launches & 1), c->n, c->stream)) != hipSuccess)
             return lbm_hip_fail(e, "drag reduction");
         for (int m = 0; m < c->n; ++m)
             if (c->h_active[m]) {
-                c->h_parity[m] ^= (chunk & 1);
+                c->h_parity[m] ^= (launches & 1);
                 c->h_cursor[m] += chunk;
             }
         done += chunk;
@@ -391,6 +429,12 @@ extern "C" int lbm_flags(const lbm_ctx* c, int32_t* out_dev) {
 
 extern "C" int32_t lbm_tile_count(void) { return N_TILE_SHAPES; }
 
+extern "C" int lbm_launch_steps(const lbm_ctx* c, int32_t* steps) {
+    if (!c || !steps) return lbm_fail(LBM_EINVAL, "NULL argument");
+    *steps = c->two_step ? 2 : 1;
+    return LBM_OK;
+}
+
 extern "C" int lbm_set_tile(lbm_ctx* c, int32_t tile_id) {
     if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     if (tile_id < 0 || tile_id >= N_TILE_SHAPES) return lbm_fail(LBM_EINVAL, "tile id %d out of range", tile_id);
@@ -414,34 +458,38 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     a.pop0 = c->pop[0];
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
-    // Steps are timed in pairs so every state ends in the buffer it started
-    // in; the states do advance (untracked: no drag, no cursor), so callers
-    // tune before lbm_init, which rebuilds step 0.
+    // Launches are timed in pairs so every state ends in the buffer it
+    // started in; the states do advance (untracked: no drag, no cursor), so
+    // callers tune before lbm_init, which rebuilds step 0.
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return lbm_fail(LBM_EHIP, "event creation failed");
-    float best_ms = 1e30f;
+    float best_ms = 1e30f;  // per step
     int best = c->tile_id;
     const int pairs = std::max(1, n_steps / 2);
     for (int t = 0; t < N_TILE_SHAPES; ++t) {
         c->tile_id = t;
         if (build_segments(c) != LBM_OK) continue;
-        a.total_blocks = c->total_blocks;
-        a.xcd = TILE_SHAPES[t].xcd;
-        a.nseg = c->nseg;
-        for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
+        const TileShape ts = TILE_SHAPES[t];
+        if (ts.steps == 2 && !c->two_step) continue;  // it would run shape 0
+        const bool two = ts.steps == 2;
+        a.total_blocks = two ? c->total_blocks2 : c->total_blocks;
+        a.xcd = ts.xcd;
+        a.nseg = two ? c->nseg2 : c->nseg;
+        for (int s = 0; s < a.nseg; ++s) a.seg[s] = two ? c->seg2[s] : c->seg[s];
         a.slot = 0;
+        auto launch = [&](int flip) {
+            a.flip = flip;
+            return two ? launch_step2(ts.tyt, a, c->stream) : launch_step(t, a, c->stream);
+        };
         // warm-up pair
-        for (int s = 0; s < 2; ++s) {
-            a.flip = s;
-            launch_step(t, a, c->stream);
-        }
+        launch(0);
+        launch(1);
         hipEventRecord(e0, c->stream);
-        for (int p = 0; p < pairs; ++p)
-            for (int s = 0; s < 2; ++s) {
-                a.flip = s;
-                launch_step(t, a, c->stream);
-            }
+        for (int p = 0; p < pairs; ++p) {
+            launch(0);
+            launch(1);
+        }
         hipEventRecord(e1, c->stream);
         hipError_t err = hipEventSynchronize(e1);
         if (err != hipSuccess) {
@@ -451,6 +499,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         }
         float ms = 0;
         hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)(2 * pairs * ts.steps);
         if (ms < best_ms) {
             best_ms = ms;
             best = t;

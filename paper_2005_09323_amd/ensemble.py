@@ -91,6 +91,12 @@ class Ensemble:
     def set_tile(self, tile_id: int) -> None:
         native.check(self.lib.lbm_set_tile(self._ctx, tile_id))
 
+    def launch_steps(self) -> int:
+        """Lattice steps per launch of the shape in use (2 for the two-step kernel)."""
+        n = ctypes.c_int32()
+        native.check(self.lib.lbm_launch_steps(self._ctx, ctypes.byref(n)))
+        return n.value
+
     def autotune(self, n_steps: int = 20) -> int:
         best = ctypes.c_int32()
         native.check(self.lib.lbm_autotune(self._ctx, n_steps, ctypes.byref(best)))

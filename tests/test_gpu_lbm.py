@@ -97,6 +97,77 @@ def test_ragged_mixed_shapes_all_tiles():
             assert np.array_equal(states[i][:, fluid], states0[i][:, fluid])
 
 
+def _two_step_tiles():
+    from paper_2005_09323_amd import native
+    lib = native.lib()
+    return [t for t in range(lib.lbm_tile_count()) if t >= 16]
+
+
+def test_two_step_shapes_bit_identical_to_one_step():
+    """Widths that are multiples of 256: the two-step kernel (every shape) against shape 0, bit for bit.
+
+    Squares straddling a strip boundary and next to the periodic edges, a lattice lower than
+    the rows per iteration, and an odd step count (chunks that end with a single step)."""
+    members = [workloads.Member(256, 37, 0.6, 2e-5, (50, 10, 6)),
+               workloads.Member(512, 21, 0.53, 1e-5, (253, 8, 6)),
+               workloads.Member(256, 12, 0.56, 3e-5, (1, 1, 3)),
+               workloads.Member(256, 12, 0.56, 3e-5, (251, 7, 4)),
+               workloads.Member(768, 5, 0.7, 4e-5, None),
+               workloads.Member(256, 16, 0.52, 1e-5, (120, 5, 6))]
+    steps = 301
+    results = {}
+    for tile in [0] + _two_step_tiles():
+        ens = _ensemble(members, steps)
+        ens.set_tile(tile)
+        ens.init(13, 1e-2)
+        ens.step(steps - 1)
+        torch.cuda.synchronize()
+        results[tile] = (ens.drag(0, steps).cpu().numpy(),
+                         [ens.state(i).cpu().numpy().copy() for i in range(len(members))],
+                         [ens.time(i) for i in range(len(members))])
+        ens.close()
+    drag0, states0, times0 = results[0]
+    assert times0 == [steps] * len(members)
+    for i, m in enumerate(members):
+        if m.square is None:
+            assert np.all(drag0[i] == 0)
+            continue
+        fout, ref = _oracle(m, 13, i, 1e-2, steps)
+        assert _rel(drag0[i], ref) <= 1e-5, i
+    for tile, (drag, states, times) in results.items():
+        assert times == times0, tile
+        assert np.array_equal(drag, drag0), tile
+        for i, m in enumerate(members):
+            fluid = ~olbm.solid_mask(_channel(m))
+            assert np.array_equal(states[i][:, fluid], states0[i][:, fluid]), (tile, i)
+
+
+def test_two_step_with_inactive_members_and_odd_batches():
+    """Per-member stepping (set_active) and batches of 1, 2 and 63 steps on the two-step shape."""
+    m = workloads.Member(512, 40, 0.55, 2e-5, (100, 15, 8))
+    runs = []
+    for tile in (0, _two_step_tiles()[0]):
+        ens = _ensemble([m] * 3, 400)
+        ens.set_tile(tile)
+        ens.init(21, 1e-2)
+        ens.step(1)
+        ens.set_active([1, 0, 1])
+        ens.step(2)
+        ens.step(63)
+        ens.set_active(None)
+        ens.step(65)
+        torch.cuda.synchronize()
+        runs.append(([ens.time(i) for i in range(3)], ens.drag(0, 132).cpu().numpy(),
+                     [ens.state(i).cpu().numpy().copy() for i in range(3)]))
+        ens.close()
+    (t0, d0, s0), (t1, d1, s1) = runs
+    assert t0 == t1 == [132, 67, 132]
+    assert np.array_equal(d0[[0, 2]], d1[[0, 2]]) and np.array_equal(d0[1, :67], d1[1, :67])
+    fluid = ~olbm.solid_mask(_channel(m))
+    for i in range(3):
+        assert np.array_equal(s0[i][:, fluid], s1[i][:, fluid]), i
+
+
 def test_rest_state_exact_and_deterministic():
     m = workloads.Member(256, 64, 0.51, 0.0, (60, 28, 8))
     ens = _ensemble([m, m], 50)
@@ -144,6 +215,20 @@ def test_full_ensemble_1024_against_stored_oracle(member, name):
     gpu = ens.drag(0, 1000).cpu().numpy()
     ref = _golden(name)
     assert _rel(gpu[member], ref) <= 1e-5
+    ens.close()
+
+
+def test_full_ensemble_1024_two_step_against_stored_oracle():
+    """The two-step kernel on the whole 128 x 1024 x 256 ensemble, members 0 and 127, 1000 steps."""
+    wl = workloads.ensemble_1024()
+    ens = _ensemble(wl.members, 1000)
+    ens.set_tile(_two_step_tiles()[0])
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(999)
+    gpu = ens.drag(0, 1000).cpu().numpy()
+    assert _rel(gpu[0], _golden("ensemble1024_m0_drag1000.txt")) <= 1e-5
+    assert _rel(gpu[127], _golden("ensemble1024_m127_drag1000.txt")) <= 1e-5
+    assert int(ens.flags().sum()) == 0
     ens.close()
 
 
