@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--tile", type=int, default=16,
                     help="lattice launch shape (-1: autotune; 16, two steps per launch, is the profiled default)")
     ap.add_argument("--cpu-steps", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_ensemble1024_traffic.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_ensemble1024_traffic.json"))
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
                     help="copy: time a plain device copy of --copy-mib MiB (counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=2048)

@@ -41,7 +41,10 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Row loads of row y from the state at t: direction i comes from row y - c_iy
-// (or, next to a wall, from the row's own opposite population).
+// (or, next to a wall, from the row's own opposite population).  The loads go
+// through L2 (not non-temporal): the neighbouring strip, on the same XCD and
+// near the same row, reads the words just outside this strip, and finds them
+// there (measured: 7 % instead of 12 % extra HBM fetch, 1.6 % faster).
 __device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsrc_t rs, unsigned voff, int xl, int xr,
                                          int y, RowLoads& L) {
     const unsigned plane = (unsigned)m.nx * (unsigned)m.ny;
@@ -51,7 +54,7 @@ __device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsr
         const int ys = y - CY[i];
         const bool wall = ys < 0 || ys >= m.ny;
         const unsigned row = wall ? (unsigned)OPP[i] * plane + rowoff : (unsigned)i * plane + (unsigned)ys * (unsigned)m.nx;
-        L.v[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * row, BUFFER_NT);
+        L.v[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * row, 0);
         L.e[i] = CX[i] == 1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0))
                             : (CX[i] == -1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0))
                                            : 0.0f);
