@@ -64,6 +64,8 @@ class Channel:
     tau: float
     force_x: float
     square: Optional[Tuple[int, int, int]] = None  # (x0, y0, side) of the solid block
+    # None: BGK.  (s_b, s_3, s_4): central-moment relaxation (``oracle.central_moments``)
+    collision: Optional[Tuple[float, float, float]] = None
 
     @property
     def nu(self) -> float:
@@ -119,7 +121,12 @@ def momentum(f):
 
 
 def collide(ch: Channel, f: np.ndarray) -> np.ndarray:
-    """BGK relaxation with Guo forcing on the fluid cells; solid cells stay zero."""
+    """BGK relaxation with Guo forcing on the fluid cells; solid cells stay zero.
+
+    A channel with ``collision`` set relaxes in central moments instead."""
+    if ch.collision is not None:
+        from . import central_moments
+        return central_moments.collide(ch, f)
     solid = solid_mask(ch)
     rho = density(f)
     rho_safe = np.where(solid, 1.0, rho)
