@@ -171,6 +171,8 @@ def main():
                     help="copy: time a plain device copy of --copy-mib MiB (counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--no-legs", action="store_true", help="skip the GKTL / AMS / score-network legs")
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "central"],
+                    help="collision operator (central: central moments, unit bulk / higher-order rates)")
     args = ap.parse_args()
     if args.mode == "copy":
         return copy_calibration(args.copy_mib, max(args.steps, 1))
@@ -188,6 +190,8 @@ def main():
     ens = Ensemble(wl.members, series_capacity=total + 1)
     tile = ens.autotune(8) if args.tile < 0 else args.tile
     ens.set_tile(tile)
+    if args.collision == "central":
+        ens.set_collision("central", 1.0, 1.0, 1.0)
     ens.init(wl.seed, wl.noise_amp)
     ens.step(args.warmup)
     torch.cuda.synchronize()
@@ -221,7 +225,8 @@ def main():
     if os.path.exists(args.traffic_json):
         tj = json.load(open(args.traffic_json))
         same_kernel = kernel_sources_sha256().startswith(tj.get("kernel_sources_sha256_prefix", "-"))
-        if tj.get("workload") == wl.name and same_kernel and tile == tj.get("tile_id"):
+        if (tj.get("workload") == wl.name and same_kernel and tile == tj.get("tile_id")
+                and args.collision == tj.get("collision", "bgk")):
             traffic = tj.get("bytes_per_launch")
 
     out = {
@@ -239,7 +244,8 @@ def main():
         "data": "synthetic: seeded Philox density noise +-1e-3 on equilibrium at rest",
         "config": {"workload": wl.name, "members": len(wl.members),
                    "cells_per_step": cells, "fluid_cells_per_step": fluid,
-                   "tile_id": tile, "nonfinite_members": flags, "wall_s": round(wall, 3)},
+                   "tile_id": tile, "collision": args.collision, "nonfinite_members": flags,
+                   "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         # the same throughput priced at one HBM round trip per lattice step (72 B per fluid-cell update)

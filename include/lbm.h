@@ -156,6 +156,21 @@ int lbm_set_time(lbm_ctx* ctx, int32_t t);
 int lbm_flags(const lbm_ctx* ctx, int32_t* out_dev);
 
 /*
+ * Collision operator of every member (paper Appendix A, last paragraph: for
+ * its turbulent runs the paper relaxes in central moments instead of BGK).
+ * model 0: BGK with Guo forcing (the default; rates ignored).  model 1:
+ * central-moment multiple-relaxation-time collision with Guo forcing: the
+ * nine central moments of D2Q9 (about the Guo-shifted velocity) relax
+ * towards the central moments of the discrete second-order equilibrium and
+ * receive the central moments of Guo's source weighted by (1 - s/2); the
+ * shear moments k20 - k02 and k11 relax at 1/tau (the viscosity), the trace
+ * k20 + k02 at s_bulk, k21 and k12 at s_third, k22 at s_fourth.  Rates in
+ * (0, 2); with all three equal to 1/tau the result is BGK's.  Call before
+ * lbm_init (its step 0 collides too); synchronises the context's stream.
+ */
+int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third, double s_fourth);
+
+/*
  * Launch shape of the lattice step (an index into the library's table of
  * shapes; see lbm_tile_count).  Every shape computes bit-identical states and
  * drag.  Shapes 0-15 make one step per launch (tiles of 256 columns by a few

@@ -60,6 +60,7 @@ struct lbm_ctx {
     int chunk = 64;
     double mu = 0.0, sigma = 1.0, dt = 1.0;
     int tile_id = lbm::DEFAULT_TILE;
+    int model = 0;  // collision: 0 BGK, 1 central moments (every member)
     // one-step launches: the tile shape in use (shape 0 when a two-step shape is chosen)
     int one_tile = 0;
     int nseg = 0;

@@ -67,6 +67,10 @@ struct MemberDev {
     double omega;         // 1 / tau
     double half_fx;       // F / 2 (Guo velocity shift)
     double gf3, gf9;      // (1 - omega/2) * 3F and (1 - omega/2) * 9F (Guo source)
+    double force;         // F (central-moment collision)
+    double sb, s3, s4;    // central-moment rates: trace, third order, fourth order
+    int model;            // 0: BGK; 1: central moments
+    int pad_;
     long long off;        // first float of the member in a population buffer
     long long part_off;   // first float of the member in the drag-partial buffer
 };

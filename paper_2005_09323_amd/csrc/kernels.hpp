@@ -69,10 +69,11 @@ struct TileShape {
 extern const TileShape TILE_SHAPES[];
 extern const int N_TILE_SHAPES;
 
-hipError_t launch_step(int tile_id, const StepArgs& a, hipStream_t st);
+// model: 0 BGK, 1 central moments (every member of the launch uses it)
+hipError_t launch_step(int tile_id, const StepArgs& a, int model, hipStream_t st);
 // two steps per launch, `waves` rows per iteration; the segment table must
 // describe strips of 256 columns (tiles_per_member = tiles_x = nx / 256)
-hipError_t launch_step2(int waves, const StepArgs& a, hipStream_t st);
+hipError_t launch_step2(int waves, const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, int n_members, long long max_cells, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs& a, int n_members, hipStream_t st);
 

@@ -203,6 +203,10 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
         m.half_fx = 0.5 * d.force_x;
         m.gf3 = (1.0 - 0.5 * omega) * 3.0 * d.force_x;
         m.gf9 = (1.0 - 0.5 * omega) * 9.0 * d.force_x;
+        m.force = d.force_x;
+        m.sb = m.s3 = m.s4 = 1.0;
+        m.model = 0;
+        m.pad_ = 0;
         m.off = off;
         m.part_off = part;
         off += member_floats(d);
@@ -370,12 +374,12 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
             for (; s + 1 < chunk; s += 2, ++launches) {
                 a2.slot = s;
                 a2.flip = launches & 1;
-                if ((e = launch_step2(waves2, a2, c->stream)) != hipSuccess) return lbm_hip_fail(e, "two-step kernel");
+                if ((e = launch_step2(waves2, a2, c->model, c->stream)) != hipSuccess) return lbm_hip_fail(e, "two-step kernel");
             }
         for (; s < chunk; ++s, ++launches) {
             a.slot = s;
             a.flip = launches & 1;
-            if ((e = launch_step(c->one_tile, a, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
+            if ((e = launch_step(c->one_tile, a, c->model, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
         }
         if ((e = launch_finalize(finalize_args(c, chunk, 1, launches & 1), c->n, c->stream)) != hipSuccess)
             return lbm_hip_fail(e, "drag reduction");
@@ -425,6 +429,27 @@ extern "C" int lbm_flags(const lbm_ctx* c, int32_t* out_dev) {
     if (!c || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
     hipError_t e = hipMemcpyAsync(out_dev, c->d_flags, sizeof(int) * c->n, hipMemcpyDeviceToDevice, c->stream);
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "flags copy");
+}
+
+extern "C" int lbm_set_collision(lbm_ctx* c, int32_t model, double s_bulk, double s_third, double s_fourth) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (model != 0 && model != 1) return lbm_fail(LBM_EINVAL, "collision model %d: 0 (BGK) or 1 (central moments)", model);
+    if (model == 1)
+        for (double s : {s_bulk, s_third, s_fourth})
+            if (!(s > 0.0 && s < 2.0)) return lbm_fail(LBM_EINVAL, "relaxation rate %g outside (0, 2)", s);
+    c->model = model;
+    for (auto& m : c->h_members) {
+        m.model = model;
+        if (model == 1) {
+            m.sb = s_bulk;
+            m.s3 = s_third;
+            m.s4 = s_fourth;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(c->d_members, c->h_members.data(), sizeof(MemberDev) * c->n, hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "member table upload");
 }
 
 extern "C" int32_t lbm_tile_count(void) { return N_TILE_SHAPES; }
@@ -480,7 +505,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         a.slot = 0;
         auto launch = [&](int flip) {
             a.flip = flip;
-            return two ? launch_step2(ts.tyt, a, c->stream) : launch_step(t, a, c->stream);
+            return two ? launch_step2(ts.tyt, a, c->model, c->stream) : launch_step(t, a, c->model, c->stream);
         };
         // warm-up pair
         launch(0);

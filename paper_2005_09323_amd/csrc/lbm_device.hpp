@@ -72,6 +72,110 @@ __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsign
     return drag;
 }
 
+// Central-moment multiple-relaxation-time collision with Guo forcing of one
+// cell (the collision the paper uses for its turbulent runs, Appendix A, last
+// paragraph), in deviation form and FP64:
+//   raw moments m_pq = sum_i c_ix^p c_iy^q f_i of f = w + d (w contributes
+//   1, 1/3, 1/3, 1/9 to m00, m20, m02, m22), u = (m10 + F/2, m01) / rho;
+//   central moments k_pq by the binomial shift c^p = ((c - u) + u)^p;
+//   k* = k - s (k - k^eq) + (1 - s/2) k^F, with k^eq and k^F the central
+//   moments of the discrete second-order equilibrium and of Guo's source
+//   w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F (F along x):
+//     k20^eq = k02^eq = rho/3, k11^eq = 0, k21^eq = -rho ux^2 uy,
+//     k12^eq = -rho ux uy^2, k22^eq = rho/9 + 3 rho ux^2 uy^2;
+//     k^F: k10 = F, k21 = -2 ux uy F, k12 = F/3 - uy^2 F, k22 = 4 ux uy^2 F;
+//   rates: omega for k20 - k02 and k11, sb for k20 + k02, s3 for k21 and k12,
+//   s4 for k22 (the conserved k00, k10, k01 end at rho, F/2, 0);
+//   back to raw moments by the inverse shift and to populations by the
+//   inverse of the D2Q9 raw-moment matrix.
+// With every rate equal to omega this is the BGK + Guo update.
+__device__ __forceinline__ double cm_guo(const MemberDev& m, float d[9], unsigned links) {
+    const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+    const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
+    const double dr = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;  // rho - 1
+    const double diag = (d5 + d6) + (d7 + d8);
+    const double rho = 1.0 + dr;
+    const double jx = ((d1 - d3) + (d5 - d6)) + (d8 - d7);
+    const double jy = ((d2 - d4) + (d5 - d7)) + (d6 - d8);
+    const double m20 = (1.0 / 3.0) + ((d1 + d3) + diag);
+    const double m02 = (1.0 / 3.0) + ((d2 + d4) + diag);
+    const double m11 = (d5 - d6) + (d7 - d8);
+    const double m21 = (d5 + d6) - (d7 + d8);
+    const double m12 = (d5 - d6) - (d7 - d8);
+    const double m22 = (1.0 / 9.0) + diag;
+    double inv = (double)__builtin_amdgcn_rcpf((float)rho);
+    inv = inv * (2.0 - rho * inv);
+    inv = inv * (2.0 - rho * inv);
+    const double F = m.force;
+    const double mx = jx + m.half_fx;  // rho u_x
+    const double ux = mx * inv, uy = jy * inv;
+    const double uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    // central moments (k10 = -F/2, k01 = 0)
+    const double k20 = m20 - 2.0 * ux * jx + uxx * rho;
+    const double k02 = m02 - 2.0 * uy * jy + uyy * rho;
+    const double k11 = m11 - ux * jy - uy * jx + uxy * rho;
+    const double k21 = m21 - 2.0 * ux * m11 - uy * m20 + uxx * jy + 2.0 * uxy * jx - uxx * uy * rho;
+    const double k12 = m12 - 2.0 * uy * m11 - ux * m02 + uyy * jx + 2.0 * uxy * jy - ux * uyy * rho;
+    const double k22 = m22 - 2.0 * ux * m12 - 2.0 * uy * m21 + uxx * m02 + uyy * m20 + 4.0 * uxy * m11
+                       - 2.0 * ux * uyy * jx - 2.0 * uxx * uy * jy + uxx * uyy * rho;
+    // relaxation
+    const double om = m.omega, sb = m.sb, s3 = m.s3, s4 = m.s4;
+    const double ks = (k20 + k02) - sb * ((k20 + k02) - (2.0 / 3.0) * rho);
+    const double kd = (1.0 - om) * (k20 - k02);
+    const double p20 = 0.5 * (ks + kd), p02 = 0.5 * (ks - kd);
+    const double p11 = (1.0 - om) * k11;
+    const double p21 = k21 - s3 * (k21 + rho * uxx * uy) + (1.0 - 0.5 * s3) * (-2.0 * uxy * F);
+    const double p12 = k12 - s3 * (k12 + rho * ux * uyy) + (1.0 - 0.5 * s3) * (F * (1.0 / 3.0) - uyy * F);
+    const double p22 = k22 - s4 * (k22 - rho * (1.0 / 9.0) - 3.0 * rho * uxx * uyy) + (1.0 - 0.5 * s4) * (4.0 * ux * uyy * F);
+    const double p10 = 0.5 * F;
+    // back to raw moments of the deviations (the w part removed)
+    const double M10 = p10 + mx;  // = jx + F
+    const double M01 = jy;
+    const double M20 = p20 + 2.0 * ux * p10 + uxx * rho - (1.0 / 3.0);
+    const double M02 = p02 + uyy * rho - (1.0 / 3.0);
+    const double M11 = p11 + uy * p10 + uxy * rho;
+    const double M21 = p21 + 2.0 * ux * p11 + uy * p20 + 2.0 * uxy * p10 + uxx * uy * rho;
+    const double M12 = p12 + 2.0 * uy * p11 + ux * p02 + uyy * p10 + ux * uyy * rho;
+    const double M22 = p22 + 2.0 * ux * p12 + 2.0 * uy * p21 + uxx * p02 + uyy * p20 + 4.0 * uxy * p11
+                       + 2.0 * ux * uyy * p10 + uxx * uyy * rho - (1.0 / 9.0);
+    // populations (inverse of the raw-moment matrix)
+    const double o0 = dr - M20 - M02 + M22;
+    const double o1 = 0.5 * ((M10 + M20) - (M12 + M22));
+    const double o3 = 0.5 * ((M20 - M10) + (M12 - M22));
+    const double o2 = 0.5 * ((M01 + M02) - (M21 + M22));
+    const double o4 = 0.5 * ((M02 - M01) + (M21 - M22));
+    const double o5 = 0.25 * ((M11 + M21) + (M12 + M22));
+    const double o6 = 0.25 * ((M21 - M11) + (M22 - M12));
+    const double o7 = 0.25 * ((M11 - M21) + (M22 - M12));
+    const double o8 = 0.25 * ((M12 - M11) + (M22 - M21));
+    double drag = 0.0;
+    if (links) {
+        if ((links >> 1) & 1u) drag += 2.0 * o1;
+        if ((links >> 3) & 1u) drag -= 2.0 * o3;
+        if ((links >> 5) & 1u) drag += 2.0 * o5;
+        if ((links >> 6) & 1u) drag -= 2.0 * o6;
+        if ((links >> 7) & 1u) drag -= 2.0 * o7;
+        if ((links >> 8) & 1u) drag += 2.0 * o8;
+    }
+    d[0] = (float)o0; d[1] = (float)o1; d[2] = (float)o2; d[3] = (float)o3; d[4] = (float)o4;
+    d[5] = (float)o5; d[6] = (float)o6; d[7] = (float)o7; d[8] = (float)o8;
+    return drag;
+}
+
+// The collision of a kernel instantiated for one model (0: BGK, 1: central
+// moments); the step kernels are compiled once per model so that each keeps
+// its own register allocation.
+template <int MODEL>
+__device__ __forceinline__ double collide_cell(const MemberDev& m, float d[9], unsigned links) {
+    if constexpr (MODEL == 1) return cm_guo(m, d, links);
+    else return bgk_guo(m, d, links);
+}
+
+// The member's own model, decided at run time (the one-off initial step).
+__device__ __forceinline__ double collide_member(const MemberDev& m, float d[9], unsigned links) {
+    return m.model ? cm_guo(m, d, links) : bgk_guo(m, d, links);
+}
+
 // Directions of (x, y) whose next cell lies in the square (x-moving ones only).
 __device__ __forceinline__ unsigned square_links(const MemberDev& m, int x, int y) {
     unsigned mask = 0;

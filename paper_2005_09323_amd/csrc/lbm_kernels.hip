@@ -12,6 +12,7 @@ namespace lbm {
 
 // One fluid-or-solid cell, one population per lane access: used for lattices
 // whose width is not a multiple of 4.
+template <int MODEL>
 __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
                                             double* __restrict__ part, int x, int y) {
     const int nx = m.nx, ny = m.ny;
@@ -29,7 +30,7 @@ __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __r
         dl[i] = src[idx];
     }
     const int ri = ring_index(m, x, y);
-    const double drag = bgk_guo(m, dl, ri >= 0 ? square_links(m, x, y) : 0u);
+    const double drag = collide_cell<MODEL>(m, dl, ri >= 0 ? square_links(m, x, y) : 0u);
     const long long cell = (long long)y * nx + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = dl[i];
@@ -44,6 +45,7 @@ __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __r
 // which also carries the periodic wrap at x = 0.  Likewise for c_x = -1 at
 // the right end.  Rows next to a wall are wave-uniform (the whole row
 // bounces back); only waves touching the square decide per cell.
+template <int MODEL>
 __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
                                         double* __restrict__ part, int base, int y, int lane) {
     const int nx = m.nx, ny = m.ny;
@@ -113,7 +115,7 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 #pragma unroll
         for (int i = 0; i < 9; ++i) dl[i] = p[i][k];
         const int ri = (near_sq && live && !in_square(m, x0 + k, y)) ? ring_index(m, x0 + k, y) : -1;
-        const double drag = bgk_guo(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
+        const double drag = collide_cell<MODEL>(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
 #pragma unroll
         for (int i = 0; i < 9; ++i) p[i][k] = dl[i];
         if (ri >= 0) part[ri] = drag;
@@ -138,8 +140,8 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 // w, w + TYT, ... of the tile.
 // One-row shapes are held to 96 VGPRs (5 waves per SIMD): the memory-bound
 // step needs the waves in flight more than the registers.
-template <int TYT, int R>
-__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4))) void step_kernel(StepArgs a) {
+template <int TYT, int R, int MODEL>
+__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 ? 5 : 4))) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec;
     const int mi = block_to_member(a, b, tx, ty, vec);
@@ -160,12 +162,12 @@ __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1
         const int y = ty * (TYT * R) + r * TYT + wv;
         if (y >= m.ny) break;
         if (vec) {
-            vec_row(m, src, dst, part, base, y, lane);
+            vec_row<MODEL>(m, src, dst, part, base, y, lane);
         } else {
 #pragma unroll 1
             for (int k = 0; k < 4; ++k) {
                 const int x = base + 64 * k + lane;
-                if (x < m.nx) scalar_cell(m, src, dst, part, x, y);
+                if (x < m.nx) scalar_cell<MODEL>(m, src, dst, part, x, y);
             }
         }
     }
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         d[i] = (float)(WD[i] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * u0 * u0)));
     }
     const int ri = ring_index(m, x, y);
-    const double drag = bgk_guo(m, d, ri >= 0 ? square_links(m, x, y) : 0u);
+    const double drag = collide_member(m, d, ri >= 0 ? square_links(m, x, y) : 0u);
     float* dst = a.pop0 + m.off;  // step 0 lives in buffer 0 (parity 0)
 #pragma unroll
     for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = d[i];
@@ -244,8 +246,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
 // launchers
 
 template <int TYT, int R>
-static hipError_t launch_step_t(const StepArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((step_kernel<TYT, R>), dim3(a.total_blocks), dim3(64 * TYT), 0, st, a);
+static hipError_t launch_step_t(const StepArgs& a, int model, hipStream_t st) {
+    if (model == 1)
+        hipLaunchKernelGGL((step_kernel<TYT, R, 1>), dim3(a.total_blocks), dim3(64 * TYT), 0, st, a);
+    else
+        hipLaunchKernelGGL((step_kernel<TYT, R, 0>), dim3(a.total_blocks), dim3(64 * TYT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -260,16 +265,16 @@ const TileShape TILE_SHAPES[] = {
 };
 const int N_TILE_SHAPES = (int)(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
 
-hipError_t launch_step(int tile_id, const StepArgs& a, hipStream_t st) {
+hipError_t launch_step(int tile_id, const StepArgs& a, int model, hipStream_t st) {
     switch (tile_id % 8) {
-        case 0: return launch_step_t<4, 1>(a, st);
-        case 1: return launch_step_t<4, 2>(a, st);
-        case 2: return launch_step_t<8, 1>(a, st);
-        case 3: return launch_step_t<2, 2>(a, st);
-        case 4: return launch_step_t<16, 1>(a, st);
-        case 5: return launch_step_t<1, 4>(a, st);
-        case 6: return launch_step_t<4, 4>(a, st);
-        case 7: return launch_step_t<8, 2>(a, st);
+        case 0: return launch_step_t<4, 1>(a, model, st);
+        case 1: return launch_step_t<4, 2>(a, model, st);
+        case 2: return launch_step_t<8, 1>(a, model, st);
+        case 3: return launch_step_t<2, 2>(a, model, st);
+        case 4: return launch_step_t<16, 1>(a, model, st);
+        case 5: return launch_step_t<1, 4>(a, model, st);
+        case 6: return launch_step_t<4, 4>(a, model, st);
+        case 7: return launch_step_t<8, 2>(a, model, st);
         default: return hipErrorInvalidValue;
     }
 }

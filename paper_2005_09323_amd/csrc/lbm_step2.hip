@@ -80,6 +80,7 @@ __device__ __forceinline__ void load_cell(const MemberDev& m, const float* __res
 
 // Collide the lane's four cells of row y in place; ring cells leave their
 // drag partial in part.
+template <int MODEL>
 __device__ __forceinline__ void collide_row(const MemberDev& m, f4 p[9], double* __restrict__ part, bool near_sq, int x0,
                                             int y) {
 #pragma unroll
@@ -88,14 +89,14 @@ __device__ __forceinline__ void collide_row(const MemberDev& m, f4 p[9], double*
 #pragma unroll
         for (int i = 0; i < 9; ++i) dl[i] = p[i][k];
         const int ri = (near_sq && !in_square(m, x0 + k, y)) ? ring_index(m, x0 + k, y) : -1;
-        const double drag = bgk_guo(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
+        const double drag = collide_cell<MODEL>(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
 #pragma unroll
         for (int i = 0; i < 9; ++i) p[i][k] = dl[i];
         if (ri >= 0) part[ri] = drag;
     }
 }
 
-template <int NW>
+template <int NW, int MODEL>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void step2_kernel(StepArgs a) {
     __shared__ f4 ring4[(NW + 2) * 9 * RING_ROW / 4];
     float* const ring = (float*)ring4;
@@ -174,11 +175,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         if (y + NW < ny) load_row(m, rs, voff, xl, xr, y + NW, nxt);
         if (row_a) {
             float* row = ring + (y % (NW + 2)) * 9 * RING_ROW;
-            collide_row(m, p, part0, near_sq, x0, y);
+            collide_row<MODEL>(m, p, part0, near_sq, x0, y);
 #pragma unroll
             for (int i = 0; i < 9; ++i) *(f4*)(row + i * RING_ROW + RING_CELL0 + 4 * lane) = p[i];
             // the outside cells (their drag belongs to the neighbouring strip)
-            bgk_guo(m, hv, 0u);
+            collide_cell<MODEL>(m, hv, 0u);
             if (lane < 2 && !in_square(m, xh, y)) {
                 const int at = lane ? RING_RIGHT : RING_LEFT;
 #pragma unroll
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         if (in_square(m, x0 + k - CX[i], rsrc)) p[i][k] = own[OPP[i] * RING_ROW + RING_CELL0 + 4 * lane + k];
                 }
             }
-            collide_row(m, p, part1, near_sq, x0, r);
+            collide_row<MODEL>(m, p, part1, near_sq, x0, r);
             const unsigned rowoff = (unsigned)r * (unsigned)nx;
             if (!near_sq) {
 #pragma unroll
@@ -244,16 +245,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 }
 
 template <int NW>
-static hipError_t launch_step2_t(const StepArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((step2_kernel<NW>), dim3(a.total_blocks), dim3(64 * NW), 0, st, a);
+static hipError_t launch_step2_t(const StepArgs& a, int model, hipStream_t st) {
+    if (model == 1)
+        hipLaunchKernelGGL((step2_kernel<NW, 1>), dim3(a.total_blocks), dim3(64 * NW), 0, st, a);
+    else
+        hipLaunchKernelGGL((step2_kernel<NW, 0>), dim3(a.total_blocks), dim3(64 * NW), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_step2(int waves, const StepArgs& a, hipStream_t st) {
+hipError_t launch_step2(int waves, const StepArgs& a, int model, hipStream_t st) {
     switch (waves) {
-        case 2: return launch_step2_t<2>(a, st);
-        case 4: return launch_step2_t<4>(a, st);
-        case 8: return launch_step2_t<8>(a, st);
+        case 2: return launch_step2_t<2>(a, model, st);
+        case 4: return launch_step2_t<4>(a, model, st);
+        case 8: return launch_step2_t<8>(a, model, st);
         default: return hipErrorInvalidValue;
     }
 }

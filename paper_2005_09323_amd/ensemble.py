@@ -91,6 +91,12 @@ class Ensemble:
     def set_tile(self, tile_id: int) -> None:
         native.check(self.lib.lbm_set_tile(self._ctx, tile_id))
 
+    def set_collision(self, model: str = "bgk", s_bulk: float = 1.0, s_third: float = 1.0,
+                      s_fourth: float = 1.0) -> None:
+        """'bgk' (default) or 'central' (central-moment relaxation with the given rates); before init."""
+        code = {"bgk": 0, "central": 1}[model]
+        native.check(self.lib.lbm_set_collision(self._ctx, code, s_bulk, s_third, s_fourth))
+
     def launch_steps(self) -> int:
         """Lattice steps per launch of the shape in use (2 for the two-step kernel)."""
         n = ctypes.c_int32()

@@ -27,13 +27,13 @@ def _ensemble(members, cap):
     return Ensemble(members, series_capacity=cap)
 
 
-def _channel(m):
-    return olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square)
+def _channel(m, collision=None):
+    return olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square, collision)
 
 
-def _oracle(m, seed, member_index, amp, steps):
-    ch = _channel(m)
-    f0 = olbm.init_populations(ch, olbm.init_density(ch, seed, member_index, amp))
+def _oracle(m, seed, member_index, amp, steps, collision=None, ux0=0.0):
+    ch = _channel(m, collision)
+    f0 = olbm.init_populations(ch, olbm.init_density(ch, seed, member_index, amp), ux0)
     return olbm.run(ch, f0, steps)
 
 
@@ -166,6 +166,65 @@ def test_two_step_with_inactive_members_and_odd_batches():
     fluid = ~olbm.solid_mask(_channel(m))
     for i in range(3):
         assert np.array_equal(s0[i][:, fluid], s1[i][:, fluid]), i
+
+
+CM_RATES = (1.0, 1.0, 1.0)  # bulk, third-order and fourth-order rates of the central-moment collision
+
+
+@pytest.mark.parametrize("rates", [CM_RATES, (1.3, 0.8, 1.6)])
+def test_central_moments_against_oracle_both_kernels(rates):
+    """Central-moment collision against the oracle's, on one-step and two-step launches (bit-identical)."""
+    members = [workloads.Member(256, 37, 0.52, 2e-5, (60, 12, 8)),
+               workloads.Member(512, 24, 0.505, 1e-5, (250, 8, 6))]
+    steps = 401
+    results = {}
+    for tile in (0, _two_step_tiles()[0]):
+        ens = _ensemble(members, steps)
+        ens.set_tile(tile)
+        ens.set_collision("central", *rates)
+        ens.init(17, 1e-2)
+        ens.step(steps - 1)
+        torch.cuda.synchronize()
+        results[tile] = (ens.drag(0, steps).cpu().numpy(), [ens.state(i).cpu().numpy().copy() for i in range(2)])
+        ens.close()
+    (d0, s0), (d1, s1) = results.values()
+    assert np.array_equal(d0, d1)
+    for i, m in enumerate(members):
+        fluid = ~olbm.solid_mask(_channel(m))
+        assert np.array_equal(s0[i][:, fluid], s1[i][:, fluid]), i
+        fout, ref = _oracle(m, 17, i, 1e-2, steps, collision=rates)
+        assert _rel(d0[i], ref) <= 1e-5, (i, _rel(d0[i], ref))
+        assert _rel(s0[i][:, fluid], (fout - olbm.W[:, None, None])[:, fluid]) <= 1e-4
+
+
+def test_central_moments_impulsive_start_near_half():
+    """tau = 0.5005, uniform flow started impulsively around the square: bounded, and equal to the oracle."""
+    m = workloads.Member(256, 32, 0.5005, 0.0, (30, 13, 6))
+    steps = 300
+    ens = _ensemble([m], 700)
+    ens.set_collision("central", *CM_RATES)
+    ens.init(0, 0.0, ux0=0.08)
+    ens.step(steps - 1)
+    torch.cuda.synchronize()
+    gpu = ens.drag(0, steps).cpu().numpy()[0]
+    fout, ref = _oracle(m, 0, 0, 0.0, steps, collision=CM_RATES, ux0=0.08)
+    assert _rel(gpu, ref) <= 1e-5
+    ens.step(400)
+    assert int(ens.flags().sum()) == 0
+    assert bool(torch.isfinite(ens.drag(0, 700)).all())
+    ens.close()
+
+
+def test_collision_argument_errors():
+    m = workloads.Member(256, 16, 0.6, 1e-5, None)
+    ens = _ensemble([m], 10)
+    from paper_2005_09323_amd.native import LbmError
+    for bad in ((1, 0.0, 1.0, 1.0), (1, 1.0, 2.0, 1.0), (2, 1.0, 1.0, 1.0)):
+        with pytest.raises(LbmError):
+            from paper_2005_09323_amd import native
+            native.check(native.lib().lbm_set_collision(ens._ctx, *bad))
+    ens.set_collision("bgk")
+    ens.close()
 
 
 def test_rest_state_exact_and_deterministic():
