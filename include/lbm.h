@@ -178,12 +178,15 @@ int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third
  * of 256 columns from the bottom row to the top and keeps the intermediate
  * step in on-chip memory, so the populations cross HBM once per two steps.
  * They apply when every member's width is a multiple of 256; otherwise, and
- * for the last step of an odd batch, the library steps with shape 0.  The
- * default is shape 16.
+ * for the last step of an odd batch, the library steps with shape 0.  Shape
+ * 20, the default, is shape 16 while the active members give at least two
+ * 256-column strips per compute unit and shape 0 otherwise (the few members
+ * an AMS branch re-simulates would leave most compute units idle).
  */
 int lbm_set_tile(lbm_ctx* ctx, int32_t tile_id);
 int32_t lbm_tile_count(void);
-/* Lattice steps per launch of the shape in use on this ensemble (1 or 2). */
+/* Lattice steps per launch that the next lbm_step_batch makes (1 or 2), for
+   the shape in use and the members active now. */
 int lbm_launch_steps(const lbm_ctx* ctx, int32_t* steps);
 /* Time every tile shape on this ensemble (n_steps each, on the context's
    stream, synchronising it) and keep the fastest.  Writes the chosen id. */

@@ -11,7 +11,7 @@
 namespace lbm {
 
 constexpr int MAX_MEMBERS = 4096;
-constexpr int DEFAULT_TILE = 16;  // two steps per launch (falls back to shape 0 where it does not apply)
+constexpr int DEFAULT_TILE = 20;  // two steps per launch while the active members fill the device, else one
 
 struct MaskBits {
     unsigned w[MAX_MEMBERS / 32];
@@ -61,6 +61,7 @@ struct lbm_ctx {
     double mu = 0.0, sigma = 1.0, dt = 1.0;
     int tile_id = lbm::DEFAULT_TILE;
     int model = 0;  // collision: 0 BGK, 1 central moments (every member)
+    int cu_count = 256;  // compute units of the device (the two-step kernel wants 2 workgroups per CU)
     // one-step launches: the tile shape in use (shape 0 when a two-step shape is chosen)
     int one_tile = 0;
     int nseg = 0;

@@ -132,6 +132,21 @@ static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* se
     return LBM_OK;
 }
 
+// Whether the next batch makes two steps per launch.  The two-step kernel
+// gives one workgroup per 256-column strip and sweeps all rows: with few
+// active members (an AMS branch re-simulates a handful) that leaves most
+// compute units idle, and one-step launches (many small tiles, the same
+// results bit for bit) are faster.  The adaptive shape uses it only with at
+// least 2 active strips per compute unit.
+static bool two_step_now(const lbm_ctx* c) {
+    if (!c->two_step) return false;
+    if (!TILE_SHAPES[c->tile_id].adaptive) return true;
+    long long strips = 0;
+    for (int m = 0; m < c->n; ++m)
+        if (c->h_active[m]) strips += c->desc[m].nx / 256;
+    return strips >= 2LL * c->cu_count;
+}
+
 // Tables of the current tile shape.  A two-step shape applies when every
 // member's width is a multiple of 256 and its block fits 32-bit byte
 // offsets; otherwise (and for the last step of an odd chunk) the library
@@ -216,6 +231,12 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
     }
     c->partial_floats = std::max<long long>(part, 1);
     c->tile_id = DEFAULT_TILE;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->cu_count = cus;
+    }
     int rc = build_segments(c);
     if (rc) {
         delete c;
@@ -364,13 +385,14 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
         for (int s = 0; s < c->nseg2; ++s) a2.seg[s] = c->seg2[s];
     }
     const int waves2 = TILE_SHAPES[c->tile_id].tyt;
+    const bool two = two_step_now(c);
     hipError_t e;
     int done = 0;
     while (done < n_steps) {
         const int chunk = std::min(n_steps - done, c->chunk);
         // every launch swaps the buffers once, whether it makes one step or two
         int launches = 0, s = 0;
-        if (c->two_step)
+        if (two)
             for (; s + 1 < chunk; s += 2, ++launches) {
                 a2.slot = s;
                 a2.flip = launches & 1;
@@ -456,7 +478,7 @@ extern "C" int32_t lbm_tile_count(void) { return N_TILE_SHAPES; }
 
 extern "C" int lbm_launch_steps(const lbm_ctx* c, int32_t* steps) {
     if (!c || !steps) return lbm_fail(LBM_EINVAL, "NULL argument");
-    *steps = c->two_step ? 2 : 1;
+    *steps = two_step_now(c) ? 2 : 1;
     return LBM_OK;
 }
 
@@ -497,6 +519,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         if (build_segments(c) != LBM_OK) continue;
         const TileShape ts = TILE_SHAPES[t];
         if (ts.steps == 2 && !c->two_step) continue;  // it would run shape 0
+        if (ts.adaptive) continue;                    // a policy over shapes 16 and 0, not a shape
         const bool two = ts.steps == 2;
         a.total_blocks = two ? c->total_blocks2 : c->total_blocks;
         a.xcd = ts.xcd;

@@ -257,11 +257,15 @@ static hipError_t launch_step_t(const StepArgs& a, int model, hipStream_t st) {
 // Table of step-kernel launch shapes: TYT waves per workgroup, R rows per
 // wave, whether workgroups are remapped so each XCD gets contiguous tiles,
 // and steps per launch.  Ids 0-15 are one-step shapes (launch_step switches
-// on id % 8); ids 16-19 are the two-step kernel with TYT rows per iteration.
+// on id % 8); ids 16-19 are the two-step kernel with TYT rows per iteration;
+// id 20 is shape 16 while the active members fill the device, shape 0 otherwise.
 const TileShape TILE_SHAPES[] = {
-    {4, 1, 1, 1}, {4, 2, 1, 1}, {8, 1, 1, 1}, {2, 2, 1, 1}, {16, 1, 1, 1}, {1, 4, 1, 1}, {4, 4, 1, 1}, {8, 2, 1, 1},
-    {4, 1, 0, 1}, {4, 2, 0, 1}, {8, 1, 0, 1}, {2, 2, 0, 1}, {16, 1, 0, 1}, {1, 4, 0, 1}, {4, 4, 0, 1}, {8, 2, 0, 1},
-    {4, 1, 1, 2}, {2, 1, 1, 2}, {8, 1, 1, 2}, {4, 1, 0, 2},
+    {4, 1, 1, 1, 0}, {4, 2, 1, 1, 0}, {8, 1, 1, 1, 0}, {2, 2, 1, 1, 0},
+    {16, 1, 1, 1, 0}, {1, 4, 1, 1, 0}, {4, 4, 1, 1, 0}, {8, 2, 1, 1, 0},
+    {4, 1, 0, 1, 0}, {4, 2, 0, 1, 0}, {8, 1, 0, 1, 0}, {2, 2, 0, 1, 0},
+    {16, 1, 0, 1, 0}, {1, 4, 0, 1, 0}, {4, 4, 0, 1, 0}, {8, 2, 0, 1, 0},
+    {4, 1, 1, 2, 0}, {2, 1, 1, 2, 0}, {8, 1, 1, 2, 0}, {4, 1, 0, 2, 0},
+    {4, 1, 1, 2, 1},
 };
 const int N_TILE_SHAPES = (int)(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
 

@@ -100,7 +100,7 @@ def test_ragged_mixed_shapes_all_tiles():
 def _two_step_tiles():
     from paper_2005_09323_amd import native
     lib = native.lib()
-    return [t for t in range(lib.lbm_tile_count()) if t >= 16]
+    return [t for t in range(16, min(20, lib.lbm_tile_count()))]  # 20 is the adaptive default
 
 
 def test_two_step_shapes_bit_identical_to_one_step():
@@ -225,6 +225,39 @@ def test_collision_argument_errors():
             native.check(native.lib().lbm_set_collision(ens._ctx, *bad))
     ens.set_collision("bgk")
     ens.close()
+
+
+def test_adaptive_default_shape():
+    """The default shape makes two steps per launch while the active members fill the device and
+    one step otherwise; either way the states equal those of the one-step shape 0."""
+    wl = workloads.ensemble_1024()
+    few = [1] * 8 + [0] * (len(wl.members) - 8)
+    runs = []
+    for tile in (None, 0):
+        ens = _ensemble(wl.members, 20)
+        if tile is not None:
+            ens.set_tile(tile)
+        ens.init(wl.seed, wl.noise_amp)
+        if tile is None:
+            assert ens.launch_steps() == 2
+        ens.step(4)
+        ens.set_active(few)
+        if tile is None:
+            assert ens.launch_steps() == 1
+        ens.step(5)
+        ens.set_active(None)
+        ens.step(3)
+        torch.cuda.synchronize()
+        runs.append(([ens.time(i) for i in (0, 8)], ens.drag(0, 13).cpu().numpy()[[0, 7, 8, 127]],
+                     [ens.state(i).cpu().numpy().copy() for i in (0, 8)]))
+        ens.close()
+        torch.cuda.empty_cache()
+    (t0, d0, s0), (t1, d1, s1) = runs
+    assert t0 == t1 == [13, 8]
+    assert np.array_equal(d0[:, :8], d1[:, :8]) and np.array_equal(d0[:2], d1[:2])
+    fluid = ~olbm.solid_mask(_channel(wl.members[0]))
+    for a, b in zip(s0, s1):
+        assert np.array_equal(a[:, fluid], b[:, fluid])
 
 
 def test_rest_state_exact_and_deterministic():
