@@ -20,7 +20,8 @@ struct MaskBits {
 hipError_t fill_int(int* p, int n, int v, hipStream_t st);
 hipError_t fill_double(double* p, int n, double v, hipStream_t st);
 hipError_t set_int(int* p, int v, hipStream_t st);
-hipError_t set_bits(int* p, int n, const MaskBits& bits, hipStream_t st);
+// p[m] = bit m; list (if non-null) = the set members in increasing order
+hipError_t set_bits(int* p, int* list, int n, const MaskBits& bits, hipStream_t st);
 
 }  // namespace lbm
 
@@ -49,6 +50,8 @@ struct lbm_ctx {
     int* d_parity = nullptr;
     int* d_cursor = nullptr;
     int* d_active = nullptr;
+    int* d_active_list = nullptr;  // active members in order (valid while n_active < n)
+    int n_active = 0;
     int* d_flags = nullptr;
     std::vector<int> h_parity, h_cursor, h_active;
     double* d_partial = nullptr;

@@ -31,6 +31,9 @@ struct StepArgs {
     int total_blocks;
     int nseg;
     Segment seg[MAX_SEGMENTS];
+    // non-null: the launch covers only these members (all of seg[0]'s shape),
+    // tiles_per_member workgroups each, in list order
+    const int* active_list;
 };
 
 struct InitArgs {

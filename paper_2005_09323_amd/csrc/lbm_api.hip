@@ -47,9 +47,16 @@ __global__ void fill_double_kernel(double* p, int n, double v) {
     if (i < n) p[i] = v;
 }
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
-__global__ void set_bits_kernel(int* p, int n, MaskBits bits) {
+__global__ void set_bits_kernel(int* p, int* list, int n, MaskBits bits) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n) p[i] = (int)((bits.w[i >> 5] >> (i & 31)) & 1u);
+    if (i >= n) return;
+    const unsigned on = (bits.w[i >> 5] >> (i & 31)) & 1u;
+    p[i] = (int)on;
+    if (list && on) {  // position = set bits below i
+        int pos = __popc(bits.w[i >> 5] & ((1u << (i & 31)) - 1u));
+        for (int w = 0; w < (i >> 5); ++w) pos += __popc(bits.w[w]);
+        list[pos] = i;
+    }
 }
 
 hipError_t fill_int(int* p, int n, int v, hipStream_t st) {
@@ -66,8 +73,8 @@ hipError_t set_int(int* p, int v, hipStream_t st) {
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, p, v);
     return hipGetLastError();
 }
-hipError_t set_bits(int* p, int n, const MaskBits& bits, hipStream_t st) {
-    hipLaunchKernelGGL(set_bits_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, bits);
+hipError_t set_bits(int* p, int* list, int n, const MaskBits& bits, hipStream_t st) {
+    hipLaunchKernelGGL(set_bits_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, list, n, bits);
     return hipGetLastError();
 }
 
@@ -248,6 +255,7 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
         (e = hipMalloc(&c->d_parity, sizeof(int) * n_members)) != hipSuccess ||
         (e = hipMalloc(&c->d_cursor, sizeof(int) * n_members)) != hipSuccess ||
         (e = hipMalloc(&c->d_active, sizeof(int) * n_members)) != hipSuccess ||
+        (e = hipMalloc(&c->d_active_list, sizeof(int) * n_members)) != hipSuccess ||
         (e = hipMalloc(&c->d_flags, sizeof(int) * n_members)) != hipSuccess ||
         (e = hipMalloc(&c->d_partial, sizeof(double) * c->partial_floats)) != hipSuccess ||
         (e = hipMalloc(&c->d_scratch, sizeof(double) * (4 * (size_t)n_members + 64))) != hipSuccess ||
@@ -267,6 +275,7 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
         lbm_destroy(c);
         return lbm_hip_fail(e, "initialising bookkeeping");
     }
+    c->n_active = n_members;
     *out = c;
     return LBM_OK;
 }
@@ -278,6 +287,7 @@ extern "C" int lbm_destroy(lbm_ctx* c) {
     hipFree(c->d_parity);
     hipFree(c->d_cursor);
     hipFree(c->d_active);
+    hipFree(c->d_active_list);
     hipFree(c->d_flags);
     hipFree(c->d_partial);
     hipFree(c->d_scratch);
@@ -322,6 +332,7 @@ extern "C" int lbm_init_flow(lbm_ctx* c, uint64_t seed, double noise_amp, double
         return lbm_hip_fail(e, "lbm_init bookkeeping");
     std::fill(c->h_parity.begin(), c->h_parity.end(), 0);
     std::fill(c->h_active.begin(), c->h_active.end(), 1);
+    c->n_active = c->n;
     InitArgs a;
     a.members = c->d_members;
     a.pop0 = c->pop[0];
@@ -349,12 +360,14 @@ extern "C" int lbm_set_observable(lbm_ctx* c, double mu, double sigma, double dt
 extern "C" int lbm_set_active(lbm_ctx* c, const int32_t* active_host) {
     if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     MaskBits bits{};
+    c->n_active = 0;
     for (int m = 0; m < c->n; ++m) {
         const int on = active_host ? (active_host[m] != 0) : 1;
         c->h_active[m] = on;
+        c->n_active += on;
         if (on) bits.w[m >> 5] |= 1u << (m & 31);
     }
-    hipError_t e = set_bits(c->d_active, c->n, bits, c->stream);
+    hipError_t e = set_bits(c->d_active, c->d_active_list, c->n, bits, c->stream);
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "active mask upload");
 }
 
@@ -386,6 +399,19 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
     }
     const int waves2 = TILE_SHAPES[c->tile_id].tyt;
     const bool two = two_step_now(c);
+    a.active_list = nullptr;
+    a2.active_list = nullptr;
+    if (c->n_active == 0) return LBM_OK;  // nothing steps (no drag column either)
+    if (c->n_active < c->n && c->uniform_shape) {
+        // launch the active members' tiles only: the inactive ones would cost a
+        // workgroup dispatch each (the grid of a full ensemble) for no work
+        a.active_list = c->d_active_list;
+        a.total_blocks = c->n_active * c->seg[0].tiles_per_member;
+        if (c->two_step) {
+            a2.active_list = c->d_active_list;
+            a2.total_blocks = c->n_active * c->seg2[0].tiles_per_member;
+        }
+    }
     hipError_t e;
     int done = 0;
     while (done < n_steps) {
@@ -505,6 +531,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     a.pop0 = c->pop[0];
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
+    a.active_list = nullptr;  // every member, whatever the mask
     // Launches are timed in pairs so every state ends in the buffer it
     // started in; the states do advance (untracked: no drag, no cursor), so
     // callers tune before lbm_init, which rebuilds step 0.

@@ -86,8 +86,8 @@ __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsign
 //     k^F: k10 = F, k21 = -2 ux uy F, k12 = F/3 - uy^2 F, k22 = 4 ux uy^2 F;
 //   rates: omega for k20 - k02 and k11, sb for k20 + k02, s3 for k21 and k12,
 //   s4 for k22 (the conserved k00, k10, k01 end at rho, F/2, 0);
-//   back to raw moments by the inverse shift and to populations by the
-//   inverse of the D2Q9 raw-moment matrix.
+//   the increments k* - k go back to raw moments by the inverse shift and to
+//   population increments by the inverse of the D2Q9 raw-moment matrix.
 // With every rate equal to omega this is the BGK + Guo update.
 __device__ __forceinline__ double cm_guo(const MemberDev& m, float d[9], unsigned links) {
     const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
@@ -118,36 +118,34 @@ __device__ __forceinline__ double cm_guo(const MemberDev& m, float d[9], unsigne
     const double k12 = m12 - 2.0 * uy * m11 - ux * m02 + uyy * jx + 2.0 * uxy * jy - ux * uyy * rho;
     const double k22 = m22 - 2.0 * ux * m12 - 2.0 * uy * m21 + uxx * m02 + uyy * m20 + 4.0 * uxy * m11
                        - 2.0 * ux * uyy * jx - 2.0 * uxx * uy * jy + uxx * uyy * rho;
-    // relaxation
+    // relaxation, as increments dk = -s (k - k^eq) + (1 - s/2) k^F of the
+    // central moments (k10 goes from -F/2 to F/2: dk10 = F)
     const double om = m.omega, sb = m.sb, s3 = m.s3, s4 = m.s4;
-    const double ks = (k20 + k02) - sb * ((k20 + k02) - (2.0 / 3.0) * rho);
-    const double kd = (1.0 - om) * (k20 - k02);
-    const double p20 = 0.5 * (ks + kd), p02 = 0.5 * (ks - kd);
-    const double p11 = (1.0 - om) * k11;
-    const double p21 = k21 - s3 * (k21 + rho * uxx * uy) + (1.0 - 0.5 * s3) * (-2.0 * uxy * F);
-    const double p12 = k12 - s3 * (k12 + rho * ux * uyy) + (1.0 - 0.5 * s3) * (F * (1.0 / 3.0) - uyy * F);
-    const double p22 = k22 - s4 * (k22 - rho * (1.0 / 9.0) - 3.0 * rho * uxx * uyy) + (1.0 - 0.5 * s4) * (4.0 * ux * uyy * F);
-    const double p10 = 0.5 * F;
-    // back to raw moments of the deviations (the w part removed)
-    const double M10 = p10 + mx;  // = jx + F
-    const double M01 = jy;
-    const double M20 = p20 + 2.0 * ux * p10 + uxx * rho - (1.0 / 3.0);
-    const double M02 = p02 + uyy * rho - (1.0 / 3.0);
-    const double M11 = p11 + uy * p10 + uxy * rho;
-    const double M21 = p21 + 2.0 * ux * p11 + uy * p20 + 2.0 * uxy * p10 + uxx * uy * rho;
-    const double M12 = p12 + 2.0 * uy * p11 + ux * p02 + uyy * p10 + ux * uyy * rho;
-    const double M22 = p22 + 2.0 * ux * p12 + 2.0 * uy * p21 + uxx * p02 + uyy * p20 + 4.0 * uxy * p11
-                       + 2.0 * ux * uyy * p10 + uxx * uyy * rho - (1.0 / 9.0);
-    // populations (inverse of the raw-moment matrix)
-    const double o0 = dr - M20 - M02 + M22;
-    const double o1 = 0.5 * ((M10 + M20) - (M12 + M22));
-    const double o3 = 0.5 * ((M20 - M10) + (M12 - M22));
-    const double o2 = 0.5 * ((M01 + M02) - (M21 + M22));
-    const double o4 = 0.5 * ((M02 - M01) + (M21 - M22));
-    const double o5 = 0.25 * ((M11 + M21) + (M12 + M22));
-    const double o6 = 0.25 * ((M21 - M11) + (M22 - M12));
-    const double o7 = 0.25 * ((M11 - M21) + (M22 - M12));
-    const double o8 = 0.25 * ((M12 - M11) + (M22 - M21));
+    const double dks = -sb * ((k20 + k02) - (2.0 / 3.0) * rho);
+    const double dkd = -om * (k20 - k02);
+    const double e20 = 0.5 * (dks + dkd), e02 = 0.5 * (dks - dkd);
+    const double e11 = -om * k11;
+    const double e21 = -s3 * (k21 + rho * uxx * uy) + (1.0 - 0.5 * s3) * (-2.0 * uxy * F);
+    const double e12 = -s3 * (k12 + rho * ux * uyy) + (1.0 - 0.5 * s3) * (F * (1.0 / 3.0) - uyy * F);
+    const double e22 = -s4 * (k22 - rho * (1.0 / 9.0) - 3.0 * rho * uxx * uyy) + (1.0 - 0.5 * s4) * (4.0 * ux * uyy * F);
+    // the same increments as raw moments (inverse shift, linear in the increments)
+    const double M10 = F;
+    const double M20 = e20 + 2.0 * ux * F;
+    const double M02 = e02;
+    const double M11 = e11 + uy * F;
+    const double M21 = e21 + 2.0 * ux * e11 + uy * e20 + 2.0 * uxy * F;
+    const double M12 = e12 + 2.0 * uy * e11 + ux * e02 + uyy * F;
+    const double M22 = e22 + 2.0 * ux * e12 + 2.0 * uy * e21 + uxx * e02 + uyy * e20 + 4.0 * uxy * e11 + 2.0 * ux * uyy * F;
+    // and as populations (inverse of the raw-moment matrix; dM00 = dM01 = 0)
+    const double o0 = d0 + ((M22 - M20) - M02);
+    const double o1 = d1 + 0.5 * ((M10 + M20) - (M12 + M22));
+    const double o3 = d3 + 0.5 * ((M20 - M10) + (M12 - M22));
+    const double o2 = d2 + 0.5 * (M02 - (M21 + M22));
+    const double o4 = d4 + 0.5 * ((M02 + M21) - M22);
+    const double o5 = d5 + 0.25 * ((M11 + M21) + (M12 + M22));
+    const double o6 = d6 + 0.25 * ((M21 - M11) + (M22 - M12));
+    const double o7 = d7 + 0.25 * ((M11 - M21) + (M22 - M12));
+    const double o8 = d8 + 0.25 * ((M12 - M11) + (M22 - M21));
     double drag = 0.0;
     if (links) {
         if ((links >> 1) & 1u) drag += 2.0 * o1;
@@ -188,6 +186,14 @@ __device__ __forceinline__ unsigned square_links(const MemberDev& m, int x, int 
 // Workgroup -> (member, tile): members are grouped in segments of equal
 // lattice shape; within a segment tiles run x-fastest, then y, then member.
 __device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx, int& ty, int& vec) {
+    if (a.active_list) {  // a subset of members of one lattice shape
+        const int k = b / a.seg[0].tiles_per_member;
+        const int tile = b - k * a.seg[0].tiles_per_member;
+        ty = tile / a.seg[0].tiles_x;
+        tx = tile - ty * a.seg[0].tiles_x;
+        vec = a.seg[0].vec;
+        return a.active_list[k];
+    }
     int s = 0;
 #pragma unroll 1
     while (s + 1 < a.nseg && b >= a.seg[s + 1].block_begin) ++s;
