@@ -252,11 +252,17 @@ def main():
         "lup_equivalent": {"steps_per_launch": per_launch, "bytes_per_lup": BYTES_PER_LUP,
                            "GBs": round(equiv, 1), "frac_of_peak": round(equiv / HBM_PEAK_GBS, 4)},
     }
+    diag_ms = None
+    if not args.no_legs:
+        ens.face_diagnostics()
+        torch.cuda.synchronize()
+        diag_ms = _timed(lambda: ens.face_diagnostics(), 10)
     ens.close()
     del ens
     torch.cuda.empty_cache()
     if not args.no_legs:
         out["legs"] = legs()
+        out["legs"]["face_diagnostics"] = {"workload": wl.name, "ms_per_call": round(diag_ms, 4)}
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -156,6 +156,25 @@ int lbm_set_time(lbm_ctx* ctx, int32_t t);
 int lbm_flags(const lbm_ctx* ctx, int32_t* out_dev);
 
 /*
+ * Pressure, stress and shear on the square's faces, for the populations the
+ * next step collides (paper Section 2.1: the drag as the surface integral of
+ * the stress of Appendix A, and its forebody-minus-base pressure
+ * approximation; Section 3.2.2: the mean shear along the top or bottom face).
+ * Each face is represented by the s fluid cells adjacent to it.  Writes
+ * out_dev[m * 5 + q] (device FP64) for every member m:
+ *   q = 0  p_fb   = sum over the front cells of c_s^2 rho
+ *   q = 1  p_base = sum over the base cells of c_s^2 rho
+ *   q = 2  drag from the stress: sum of tau_xb n_b over the four faces (n the
+ *          square's outward normal), tau_ab = -c_s^2 rho delta_ab
+ *          - (1 - 1/(2 tau)) sum_i c_ia c_ib (f_i - f_i^eq)
+ *   q = 3  mean shear on top:    (1/s) sum u_x over the top cells / (1/2)
+ *   q = 4  mean shear on bottom: (1/s) sum (-u_x) over the bottom cells / (1/2)
+ * with u the Guo-shifted velocity; zeros for members without a square.
+ * Enqueued on the context's stream.
+ */
+int lbm_face_diagnostics(const lbm_ctx* ctx, double* out_dev);
+
+/*
  * Collision operator of every member (paper Appendix A, last paragraph: for
  * its turbulent runs the paper relaxes in central moments instead of BGK).
  * model 0: BGK with Guo forcing (the default; rates ignored).  model 1:

@@ -174,6 +174,23 @@ __device__ __forceinline__ double collide_member(const MemberDev& m, float d[9],
     return m.model ? cm_guo(m, d, links) : bgk_guo(m, d, links);
 }
 
+// The nine pulled populations of one cell (x, y) from the state at t, with
+// periodic x, wall rows and the obstacle bouncing back (per-lane gathers).
+__device__ __forceinline__ void load_cell(const MemberDev& m, const float* __restrict__ src, int x, int y, float dl[9]) {
+    const int nx = m.nx, ny = m.ny;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int xs = x - CX[i];
+        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+        const int ys = y - CY[i];
+        const bool bounce = (ys < 0) | (ys >= ny) | in_square(m, xs, ys);
+        const unsigned idx = bounce ? (unsigned)OPP[i] * plane + (unsigned)y * (unsigned)nx + (unsigned)x
+                                    : (unsigned)i * plane + (unsigned)ys * (unsigned)nx + (unsigned)xs;
+        dl[i] = src[idx];
+    }
+}
+
 // Directions of (x, y) whose next cell lies in the square (x-moving ones only).
 __device__ __forceinline__ unsigned square_links(const MemberDev& m, int x, int y) {
     unsigned mask = 0;

@@ -61,23 +61,6 @@ __device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsr
     }
 }
 
-// The nine pulled populations of one cell (x, y) from the state at t, with
-// periodic x, wall rows and the obstacle bouncing back (per-lane gathers).
-__device__ __forceinline__ void load_cell(const MemberDev& m, const float* __restrict__ src, int x, int y, float dl[9]) {
-    const int nx = m.nx, ny = m.ny;
-    const unsigned plane = (unsigned)nx * (unsigned)ny;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int xs = x - CX[i];
-        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        const int ys = y - CY[i];
-        const bool bounce = (ys < 0) | (ys >= ny) | in_square(m, xs, ys);
-        const unsigned idx = bounce ? (unsigned)OPP[i] * plane + (unsigned)y * (unsigned)nx + (unsigned)x
-                                    : (unsigned)i * plane + (unsigned)ys * (unsigned)nx + (unsigned)xs;
-        dl[i] = src[idx];
-    }
-}
-
 // Collide the lane's four cells of row y in place; ring cells leave their
 // drag partial in part.
 template <int MODEL>

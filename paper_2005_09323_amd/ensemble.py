@@ -91,6 +91,13 @@ class Ensemble:
     def set_tile(self, tile_id: int) -> None:
         native.check(self.lib.lbm_set_tile(self._ctx, tile_id))
 
+    def face_diagnostics(self) -> torch.Tensor:
+        """[N, 5] FP64 on the device: forebody pressure, base pressure, drag from the stress
+        integral, mean shear on the top and on the bottom face (next step's populations)."""
+        out = torch.empty((self.n, 5), dtype=torch.float64, device=self.device)
+        native.check(self.lib.lbm_face_diagnostics(self._ctx, _ptr(out)))
+        return out
+
     def set_collision(self, model: str = "bgk", s_bulk: float = 1.0, s_third: float = 1.0,
                       s_fourth: float = 1.0) -> None:
         """'bgk' (default) or 'central' (central-moment relaxation with the given rates); before init."""

@@ -55,6 +55,7 @@ _SIG = {
     "lbm_flags": (ctypes.c_int, [_P, _P]),
     "lbm_set_tile": (ctypes.c_int, [_P, _I]),
     "lbm_tile_count": (_I, []),
+    "lbm_face_diagnostics": (ctypes.c_int, [_P, _P]),
     "lbm_set_collision": (ctypes.c_int, [_P, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_launch_steps": (ctypes.c_int, [_P, ctypes.POINTER(_I)]),
     "lbm_autotune": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),

@@ -260,6 +260,33 @@ def test_adaptive_default_shape():
         assert np.array_equal(a[:, fluid], b[:, fluid])
 
 
+def test_face_diagnostics_against_oracle():
+    """Pressure, stress-integral drag and shear on the square's faces after a noisy forced run
+    (both collisions), against the oracle's on its own run."""
+    from oracle import diagnostics as odg
+    members = [workloads.Member(256, 37, 0.52, 2e-5, (60, 12, 8)),
+               workloads.Member(256, 37, 0.6, 1e-5, (120, 20, 5)),
+               workloads.Member(256, 37, 0.6, 1e-5, None)]
+    steps = 300
+    for collision in (None, CM_RATES):
+        ens = _ensemble(members, steps)
+        if collision is not None:
+            ens.set_collision("central", *collision)
+        ens.init(23, 1e-2)
+        ens.step(steps - 1)
+        gpu = ens.face_diagnostics().cpu().numpy()
+        ens.close()
+        for i, m in enumerate(members):
+            ch = _channel(m, collision)
+            fout, _ = _oracle(m, 23, i, 1e-2, steps, collision=collision)
+            ref = odg.diagnostics(ch, olbm.stream(ch, fout))
+            if m.square is None:
+                assert np.all(gpu[i] == 0)
+                continue
+            scale = np.array([ref[0], ref[0], abs(ref[2]), abs(ref[3]), abs(ref[4])])
+            assert np.all(np.abs(gpu[i] - ref) <= 1e-5 * scale), (i, gpu[i], ref)
+
+
 def test_rest_state_exact_and_deterministic():
     m = workloads.Member(256, 64, 0.51, 0.0, (60, 28, 8))
     ens = _ensemble([m, m], 50)
