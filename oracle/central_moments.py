@@ -106,7 +106,7 @@ def collide(ch, f: np.ndarray) -> np.ndarray:
     """Central-moment relaxation with Guo forcing on the fluid cells; solid cells stay zero.
 
     ch.collision = (s_b, s_3, s_4); the shear rate is 1/ch.tau."""
-    from .lbm import density, equilibrium, momentum, solid_mask
+    from .lbm import density, equilibrium, momentum, relaxation_time, solid_mask
     s_b, s_3, s_4 = ch.collision
     solid = solid_mask(ch)
     rho = density(f)
@@ -116,7 +116,7 @@ def collide(ch, f: np.ndarray) -> np.ndarray:
     uy = jy / rho_safe
     k = central_moments(f, ux, uy)
     keq = central_moments(equilibrium(rho_safe, ux, uy), ux, uy)
-    kf = central_moments(guo_term(ux, uy, ch.force_x, 0.0), ux, uy)
-    fout = populations(relax(k, keq, kf, 1.0 / ch.tau, s_b, s_3, s_4), ux, uy)
+    kf = central_moments(guo_term(ux, uy, ch.force_x, 0.0), ux, uy)  # weighted per rate in relax
+    fout = populations(relax(k, keq, kf, 1.0 / relaxation_time(ch), s_b, s_3, s_4), ux, uy)
     fout[:, solid] = 0.0
     return fout

@@ -66,6 +66,8 @@ class Channel:
     square: Optional[Tuple[int, int, int]] = None  # (x0, y0, side) of the solid block
     # None: BGK.  (s_b, s_3, s_4): central-moment relaxation (``oracle.central_moments``)
     collision: Optional[Tuple[float, float, float]] = None
+    # None: periodic x.  An ``oracle.open_channel.OpenChannel``: inlet, grid, sponge, outlet
+    open: Optional[object] = None
 
     @property
     def nu(self) -> float:
@@ -74,7 +76,7 @@ class Channel:
 
 
 @lru_cache(maxsize=32)
-def _solid(ch: Channel) -> np.ndarray:
+def _square(ch: Channel) -> np.ndarray:
     m = np.zeros((ch.ny, ch.nx), dtype=bool)
     if ch.square is not None and ch.square[2] > 0:
         x0, y0, s = ch.square
@@ -83,9 +85,33 @@ def _solid(ch: Channel) -> np.ndarray:
     return m
 
 
+@lru_cache(maxsize=32)
+def _solid(ch: Channel) -> np.ndarray:
+    m = _square(ch).copy()
+    if ch.open is not None:
+        from .open_channel import grid_mask
+        m |= grid_mask(ch.ny, ch.nx, ch.open)
+    m.setflags(write=False)
+    return m
+
+
+def square_mask(ch: Channel) -> np.ndarray:
+    """Boolean [ny, nx]: True on the cells of the square, the body whose drag is measured."""
+    return _square(ch)
+
+
 def solid_mask(ch: Channel) -> np.ndarray:
-    """Boolean [ny, nx]: True on the cells of the square (read-only, cached)."""
+    """Boolean [ny, nx]: True on every solid cell (the square and, in an open channel, the
+    entrance grid's bars); read-only, cached."""
     return _solid(ch)
+
+
+def relaxation_time(ch: Channel):
+    """tau, or the [ny, nx] field of an open channel's sponge zone."""
+    if ch.open is None:
+        return ch.tau
+    from .open_channel import tau_field
+    return tau_field(ch)
 
 
 def equilibrium(rho, ux, uy):
@@ -134,8 +160,9 @@ def collide(ch: Channel, f: np.ndarray) -> np.ndarray:
     ux = (jx + 0.5 * ch.force_x) / rho_safe
     uy = (jy + 0.0) / rho_safe
     feq = equilibrium(rho_safe, ux, uy)
-    src = guo_source(ux, uy, ch.force_x, 0.0, ch.tau)
-    fout = f - (f - feq) / ch.tau + src
+    tau = relaxation_time(ch)
+    src = guo_source(ux, uy, ch.force_x, 0.0, tau)
+    fout = f - (f - feq) / tau + src
     fout[:, solid] = 0.0
     return fout
 
@@ -143,7 +170,7 @@ def collide(ch: Channel, f: np.ndarray) -> np.ndarray:
 @lru_cache(maxsize=32)
 def square_links(ch: Channel):
     """Tuple of (i, mask[ny, nx]) with mask True where fluid x has x + c_i in the square."""
-    solid = solid_mask(ch)
+    solid = square_mask(ch)
     links = []
     for i in range(1, 9):
         cx, cy = C[i]
@@ -198,7 +225,11 @@ def stream_sources(ch: Channel):
 
 
 def stream(ch: Channel, fout: np.ndarray) -> np.ndarray:
-    """Pull streaming with periodic x and halfway bounce-back at walls and square."""
+    """Pull streaming with periodic x and halfway bounce-back at walls and square
+    (an open channel streams through its inlet and outlet instead)."""
+    if ch.open is not None:
+        from . import open_channel
+        return open_channel.stream(ch, fout)
     flat = fout.reshape(9, -1)
     fnew = np.empty_like(fout)
     for i, (src_dir, src_cell) in enumerate(stream_sources(ch)):

@@ -1,0 +1,159 @@
+"""The paper's open channel: inlet, entrance grid, sponge zone, outlet, in FP64.
+
+Test infrastructure (see ``oracle/__init__``).
+
+Section 2 describes the flow: a parabolic velocity profile with unit density
+is imposed upstream of a grid of bars (bar height and spacing both R/2); near
+the end of the channel a sponge zone raises the viscosity; the outlet
+extrapolates velocity and density to second order and rebuilds the
+populations by regularisation from a finite-difference stress.  The paper
+gives no further detail (its set-up lives in its software); the reading used
+here (and by the device code):
+
+* inlet: a ghost column at x = -1 holds the equilibrium of (rho = 1,
+  u = (u_in(y), 0)), u_in(y) = 4 u_c (y + 1/2)(ny - y - 1/2) / ny^2 (zero on
+  the halfway walls); cells at x = 0 pull their +x movers from it;
+* grid: b x b solid bars at columns gx0 .. gx0 + b - 1, rows y >= b/2 with
+  (y - b/2) mod 2b < b (b = bar, integer b/2): bars and gaps of height b,
+  half gaps against the walls; halfway bounce-back on them as on the square
+  (their force is not drag);
+* sponge: tau(x) = tau + (tau_s - tau) r^2, r = (x - xs)/(nx - 1 - xs), for
+  x > xs (tau elsewhere);
+* outlet: a ghost column at x = nx holds the post-collision populations of
+  a virtual cell (what a cell at x = nx - 1 pulls), per row: rho_g = 2
+  rho(nx-1) - rho(nx-2) and u_g = 2 u(nx-1) - u(nx-2) from the post-collision
+  state (mass and momentum of a post-collision cell are those of its step),
+  the strain S from finite differences (d/dx: the extrapolation slope
+  u(nx-1) - u(nx-2); d/dy: centred differences of u_g, one-sided in the
+  first and last row), and f_i = f_i^eq(rho_g, u_g) + w_i / (2 c_s^4) Q_i : Pi
+  with Q_i = c_i c_i - c_s^2 I and Pi = -2 rho_g c_s^2 (tau - 1) S, the
+  regularised non-equilibrium second moment -2 rho c_s^2 tau S of the
+  Chapman-Enskog expansion after one relaxation (times 1 - 1/tau), tau that
+  of the outlet column;
+* x is not periodic; rows pulled from beyond a wall bounce back first.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class OpenChannel:
+    u_c: float          # inlet centre-line velocity
+    grid_x0: int        # first column of the grid bars (bar = 0: no grid)
+    bar: int            # bar height = bar width = spacing
+    sponge_x0: int      # last column before the sponge ramp (>= nx - 1: no sponge)
+    sponge_tau: float   # relaxation time at the outlet column
+
+
+def grid_mask(ny: int, nx: int, oc: OpenChannel) -> np.ndarray:
+    m = np.zeros((ny, nx), dtype=bool)
+    if oc.bar <= 0:
+        return m
+    b, off = oc.bar, oc.bar // 2
+    rows = np.array([y >= off and (y - off) % (2 * b) < b for y in range(ny)])
+    m[rows, oc.grid_x0:oc.grid_x0 + b] = True
+    return m
+
+
+def tau_field(ch) -> np.ndarray:
+    """tau(x) on [ny, nx]."""
+    oc = ch.open
+    x = np.arange(ch.nx, dtype=np.float64)
+    tau = np.full(ch.nx, ch.tau)
+    if oc.sponge_x0 < ch.nx - 1:
+        r = (x - oc.sponge_x0) / (ch.nx - 1 - oc.sponge_x0)
+        tau = np.where(x > oc.sponge_x0, ch.tau + (oc.sponge_tau - ch.tau) * r * r, ch.tau)
+    return np.repeat(tau[None, :], ch.ny, axis=0)
+
+
+def inlet_velocity(ch) -> np.ndarray:
+    y = np.arange(ch.ny) + 0.5
+    return 4.0 * ch.open.u_c * y * (ch.ny - y) / (ch.ny * ch.ny)
+
+
+def inlet_ghost(ch) -> np.ndarray:
+    """[9, ny] populations of the ghost column x = -1."""
+    from . import lbm
+    u = inlet_velocity(ch)
+    return lbm.equilibrium(np.ones(ch.ny), u, np.zeros(ch.ny))
+
+
+def outlet_ghost(ch, fout: np.ndarray) -> np.ndarray:
+    """[9, ny] populations of the ghost column x = nx from the post-collision state."""
+    from . import lbm
+    C, W, CS2 = lbm.C, lbm.W, lbm.CS2
+
+    def moments(g):
+        rho = g.sum(axis=0)
+        ux = (C[:, 0][:, None] * g).sum(axis=0) / rho
+        uy = (C[:, 1][:, None] * g).sum(axis=0) / rho
+        return rho, ux, uy
+
+    r1, ux1, uy1 = moments(fout[:, :, ch.nx - 1])
+    r2, ux2, uy2 = moments(fout[:, :, ch.nx - 2])
+    rho = np.ones_like(r1)
+    ux = 2 * ux1 - ux2
+    uy = 2 * uy1 - uy2
+
+    def ddy(v):
+        d = np.empty_like(v)
+        d[1:-1] = 0.5 * (v[2:] - v[:-2])
+        d[0] = v[1] - v[0]
+        d[-1] = v[-1] - v[-2]
+        return d
+
+    sxx = ux1 - ux2
+    syy = ddy(uy)
+    sxy = 0.5 * (ddy(ux) + (uy1 - uy2))
+    tau_out = tau_field(ch)[0, ch.nx - 1]
+    pxx = -2 * rho * CS2 * (tau_out - 1.0) * sxx
+    pyy = -2 * rho * CS2 * (tau_out - 1.0) * syy
+    pxy = -2 * rho * CS2 * (tau_out - 1.0) * sxy
+    feq = lbm.equilibrium(rho, ux, uy)
+    out = np.empty_like(feq)
+    for i in range(9):
+        cx, cy = C[i]
+        q = (cx * cx - CS2) * pxx + 2 * cx * cy * pxy + (cy * cy - CS2) * pyy
+        out[i] = feq[i] + W[i] / (2 * CS2 * CS2) * q
+    return out
+
+
+@lru_cache(maxsize=16)
+def _pull_plan(ch):
+    """Per direction: masks [ny, nx] of wall bounce, inlet, outlet, obstacle bounce, and the
+    clipped source rows / columns."""
+    from . import lbm
+    solid = lbm.solid_mask(ch)
+    ny, nx = ch.ny, ch.nx
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    plan = []
+    for i in range(9):
+        cx, cy = lbm.C[i]
+        ys, xs = yy - cy, xx - cx
+        wall = (ys < 0) | (ys >= ny)
+        inl = ~wall & (xs < 0)
+        outl = ~wall & (xs >= nx)
+        ysc, xsc = np.clip(ys, 0, ny - 1), np.clip(xs, 0, nx - 1)
+        obst = ~wall & ~inl & ~outl & solid[ysc, xsc]
+        plan.append((wall | obst, inl, outl, ysc, xsc))
+    return tuple(plan)
+
+
+def stream(ch, fout: np.ndarray) -> np.ndarray:
+    """Pull streaming with the inlet and outlet ghost columns instead of periodic x."""
+    from . import lbm
+    gin = inlet_ghost(ch)
+    gout = outlet_ghost(ch, fout)
+    fnew = np.empty_like(fout)
+    for i, (bounce, inl, outl, ysc, xsc) in enumerate(_pull_plan(ch)):
+        v = fout[i][ysc, xsc]
+        v = np.where(bounce, fout[lbm.OPP[i]], v)
+        v = np.where(inl, gin[i][ysc], v)
+        v = np.where(outl, gout[i][ysc], v)
+        fnew[i] = v
+    fnew[:, lbm.solid_mask(ch)] = 0.0
+    return fnew
