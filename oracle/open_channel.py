@@ -20,9 +20,13 @@ here (and by the device code):
 * sponge: tau(x) = tau + (tau_s - tau) r^2, r = (x - xs)/(nx - 1 - xs), for
   x > xs (tau elsewhere);
 * outlet: a ghost column at x = nx holds the post-collision populations of
-  a virtual cell (what a cell at x = nx - 1 pulls), per row: rho_g = 2
-  rho(nx-1) - rho(nx-2) and u_g = 2 u(nx-1) - u(nx-2) from the post-collision
-  state (mass and momentum of a post-collision cell are those of its step),
+  a virtual cell (what a cell at x = nx - 1 pulls), per row: density 1 and
+  u_g = 2 u(nx-1) - u(nx-2) from the post-collision state (the momentum of a
+  post-collision cell is that of its step).  The paper extrapolates the
+  density too; with the equilibrium inlet that leaves the pressure level
+  free, and the channel fills up until the flow stops (zero-gradient and
+  copied outlets) or blows up (second-order density), so the outlet holds
+  it at the inlet's value;
   the strain S from finite differences (d/dx: the extrapolation slope
   u(nx-1) - u(nx-2); d/dy: centred differences of u_g, one-sided in the
   first and last row), and f_i = f_i^eq(rho_g, u_g) + w_i / (2 c_s^4) Q_i : Pi
@@ -94,7 +98,7 @@ def outlet_ghost(ch, fout: np.ndarray) -> np.ndarray:
         return rho, ux, uy
 
     r1, ux1, uy1 = moments(fout[:, :, ch.nx - 1])
-    r2, ux2, uy2 = moments(fout[:, :, ch.nx - 2])
+    _, ux2, uy2 = moments(fout[:, :, ch.nx - 2])
     rho = np.ones_like(r1)
     ux = 2 * ux1 - ux2
     uy = 2 * uy1 - uy2
