@@ -36,6 +36,8 @@ def _workload(name):
         return workloads.mixed_sizes()
     if name == "single":
         return workloads.single_channel()
+    if name == "open":
+        return workloads.open_channel()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -45,8 +47,19 @@ def cpu_baseline(wl, steps: int):
 
     from oracle import lbm as olbm
     m = wl.members[0]
-    ch = olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square)
-    f = olbm.init_populations(ch, olbm.init_density(ch, wl.seed, 0, wl.noise_amp))
+    op = wl.extra.get("open")
+    if op is None:
+        ch = olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square)
+        f = olbm.init_populations(ch, olbm.init_density(ch, wl.seed, 0, wl.noise_amp))
+    else:
+        import numpy as np
+
+        from oracle.open_channel import OpenChannel, inlet_velocity
+        ch = olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square, wl.extra.get("rates"),
+                          open=OpenChannel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau))
+        u = np.repeat(inlet_velocity(ch)[:, None], ch.nx, axis=1)
+        f = olbm.equilibrium(olbm.init_density(ch, wl.seed, 0, wl.noise_amp), u, np.zeros_like(u))
+        f[:, olbm.solid_mask(ch)] = 0.0
     with threadpool_limits(limits=1):
         olbm.run(ch, f, 2)  # warm caches of the geometry tables
         t0 = time.perf_counter()
@@ -154,7 +167,33 @@ def legs():
                         "pictures_per_s_train": round(256 / (t_train / 1e3), 1),
                         "mfma_TFLOPs_train": round(256 * flop_train / (t_train / 1e3) / 1e12, 3),
                         "mfma_TFLOPs_forward": round(256 * flop_fwd / (t_fwd / 1e3) / 1e12, 3)}
+    del net, xt, lt
+    # the paper's open channel (inlet, grid, sponge, outlet ghost column), central moments:
+    # one step per launch plus the small ghost-column launch
+    wl = workloads.open_channel()
+    op = wl.extra["open"]
+    ens = Ensemble(wl.members, series_capacity=301)
+    ens.set_collision("central", *wl.extra["rates"])
+    ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(20)
+    torch.cuda.synchronize()
+    t_open = _timed(lambda: ens.step(256))
+    fluid = sum(m.fluid_cells for m in wl.members) - len(wl.members) * _grid_cells(wl.members[0], op)
+    gbs = BYTES_PER_LUP * fluid * 256 / (t_open / 1e3) / 1e9
+    out["open_channel"] = {"workload": wl.name, "collision": "central", "steps": 256,
+                           "ms_per_step": round(t_open / 256, 4),
+                           "MLUPS": round(wl.cells * 256 / (t_open / 1e3) / 1e6, 1),
+                           "GBs_per_step_72B": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                           "nonfinite_members": int(ens.flags().sum().item())}
+    ens.close()
     return out
+
+
+def _grid_cells(m, op) -> int:
+    """Solid cells of an open channel's entrance grid (bars of op.bar rows and columns)."""
+    b = op.bar
+    return b * sum(1 for y in range(b // 2, m.ny) if (y - b // 2) % (2 * b) < b) if b > 0 else 0
 
 
 def main():
@@ -162,7 +201,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ensemble", choices=["ensemble", "mixed", "single"])
+    ap.add_argument("--workload", default="ensemble", choices=["ensemble", "mixed", "single", "open"])
     ap.add_argument("--tile", type=int, default=16,
                     help="lattice launch shape (-1: autotune; 16, two steps per launch, is the profiled default)")
     ap.add_argument("--cpu-steps", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
@@ -192,6 +231,9 @@ def main():
     ens.set_tile(tile)
     if args.collision == "central":
         ens.set_collision("central", 1.0, 1.0, 1.0)
+    op = wl.extra.get("open")
+    if op is not None:
+        ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau)
     ens.init(wl.seed, wl.noise_amp)
     ens.step(args.warmup)
     torch.cuda.synchronize()
@@ -210,6 +252,8 @@ def main():
 
     cells = wl.cells
     fluid = sum(m.fluid_cells for m in wl.members)
+    if op is not None:
+        fluid -= len(wl.members) * _grid_cells(wl.members[0], op)
     mlups = cells * args.steps / sec / 1e6
     # the dominant kernel moves the state through HBM once per launch (72 B per
     # fluid cell) and makes `per_launch` lattice steps doing so
@@ -241,7 +285,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic: seeded Philox density noise +-1e-3 on equilibrium at rest",
+        "data": "synthetic: seeded Philox density noise +-1e-3 on equilibrium "
+                + ("at rest" if op is None else "with the inlet profile"),
         "config": {"workload": wl.name, "members": len(wl.members),
                    "cells_per_step": cells, "fluid_cells_per_step": fluid,
                    "tile_id": tile, "collision": args.collision, "nonfinite_members": flags,

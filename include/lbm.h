@@ -190,6 +190,54 @@ int lbm_face_diagnostics(const lbm_ctx* ctx, double* out_dev);
 int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third, double s_fourth);
 
 /*
+ * Open channel (paper Section 2): every member's channel is fed by an inlet
+ * and drained by an outlet instead of being periodic in x, with an entrance
+ * grid and a sponge zone.  The paper describes these only in words; the
+ * reading implemented:
+ *   inlet   ghost column x = -1 at the equilibrium of rho = 1 and
+ *           u = (u_in(y), 0), u_in(y) = 4 u_c (y + 1/2)(ny - y - 1/2) / ny^2;
+ *   grid    solid bars of grid_bar x grid_bar cells in columns grid_x0 ..
+ *           grid_x0 + grid_bar - 1, on the rows y >= grid_bar/2 (integer
+ *           division) with (y - grid_bar/2) mod (2 grid_bar) < grid_bar;
+ *           halfway bounce-back, their force is not part of the drag;
+ *           grid_bar = 0: no grid;
+ *   sponge  tau(x) = tau + (sponge_tau - tau) r^2, r = (x - sponge_x0) /
+ *           (nx - 1 - sponge_x0), for x > sponge_x0 (sponge_x0 >= nx - 1:
+ *           none); the central-moment collision takes 1/tau(x) as its
+ *           shear rate;
+ *   outlet  ghost column x = nx rebuilt before every step from the stored
+ *           state (the post-collision populations f of the last step), per
+ *           row: density 1, u_g = 2 u(nx-1) - u(nx-2) with u = sum c_i f_i /
+ *           sum f_i, strain S from differences (d/dx the extrapolation
+ *           slope, d/dy centred, one-sided in the first and last rows), and
+ *           g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) :
+ *           Pi, Pi = -2 c_s^2 (tau(nx-1) - 1) S.  (The paper extrapolates
+ *           the density too; with an equilibrium inlet that leaves the
+ *           pressure level free, so the outlet holds it at the inlet's.)
+ * Requirements (every member): grid within columns 1 .. nx - 3 and, with a
+ * square, ending at least two columns before it; the square at least two
+ * columns from the inlet (sq_x0 >= 2) and three from the outlet
+ * (sq_x0 + s <= nx - 3); 0 <= u_c <= 0.3; sponge_tau > 1/2.  The body
+ * force of the members still applies.  Open channels step one lattice step
+ * per launch (the ghost column is rebuilt between steps) plus one small
+ * launch per step for the ghost columns.  lbm_init then starts every member
+ * from the inlet profile (lbm_init_flow requires ux0 = 0).  oc = NULL
+ * restores periodic channels.  Call before lbm_init; synchronises the
+ * context's stream; allocates 9 * sum(ny) floats of library scratch for the
+ * ghost columns (freed by the next call or lbm_destroy).
+ */
+typedef struct {
+    double u_c;            /* inlet centre-line velocity */
+    int32_t grid_x0;       /* first column of the grid bars */
+    int32_t grid_bar;      /* bar height = width = gap; 0 = no grid */
+    int32_t sponge_x0;     /* last column before the sponge ramp */
+    int32_t reserved;      /* must be 0 */
+    double sponge_tau;     /* relaxation time at the outlet column, > 1/2 */
+} lbm_open_channel;
+
+int lbm_set_open_channel(lbm_ctx* ctx, const lbm_open_channel* oc);
+
+/*
  * Launch shape of the lattice step (an index into the library's table of
  * shapes; see lbm_tile_count).  Every shape computes bit-identical states and
  * drag.  Shapes 0-15 make one step per launch (tiles of 256 columns by a few

@@ -64,6 +64,10 @@ struct lbm_ctx {
     double mu = 0.0, sigma = 1.0, dt = 1.0;
     int tile_id = lbm::DEFAULT_TILE;
     int model = 0;  // collision: 0 BGK, 1 central moments (every member)
+    // open channel (every member): inlet, grid, sponge, outlet ghost columns
+    bool open = false;
+    float* d_ghost = nullptr;  // [member][9][ny] floats
+    int max_ny = 0;
     int cu_count = 256;  // compute units of the device (the two-step kernel wants 2 workgroups per CU)
     // one-step launches: the tile shape in use (shape 0 when a two-step shape is chosen)
     int one_tile = 0;

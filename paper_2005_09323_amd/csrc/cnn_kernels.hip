@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void features_kernel(FeatureArgs a) {
     for (int yy = 0; yy < a.pool; ++yy)
         for (int xx = 0; xx < a.pool; ++xx) {
             const int y = a.py0 + oy * a.pool + yy, x = a.px0 + ox * a.pool + xx;
-            if (in_square(m, x, y)) continue;  // rho = 1, u = 0 inside the obstacle
+            if (in_solid(m, x, y)) continue;  // rho = 1, u = 0 inside a solid
             const long long c = (long long)y * m.nx + x;
             double d[9];
             for (int i = 0; i < 9; ++i) d[i] = (double)st[i * plane + c];

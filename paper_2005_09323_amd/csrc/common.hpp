@@ -70,14 +70,37 @@ struct MemberDev {
     double force;         // F (central-moment collision)
     double sb, s3, s4;    // central-moment rates: trace, third order, fourth order
     int model;            // 0: BGK; 1: central moments
-    int pad_;
+    int open;             // 1: inlet, entrance grid, sponge and outlet instead of periodic x
     long long off;        // first float of the member in a population buffer
     long long part_off;   // first float of the member in the drag-partial buffer
+    // open channel (zero otherwise)
+    int gx0, bar;         // grid bars: columns gx0 .. gx0 + bar - 1 (bar = 0: no grid)
+    int sp_x0;            // last column before the sponge ramp (>= nx - 1: no sponge)
+    int pad_;
+    double tau;           // relaxation time outside the sponge
+    double tau_sp;        // relaxation time at the outlet column
+    double u_c;           // inlet centre-line velocity
+    long long ghost_off;  // first float of the member's outlet ghost column [9][ny]
 };
 
 // True if (x, y) is a cell of the member's square.
 __device__ __forceinline__ bool in_square(const MemberDev& m, int x, int y) {
     return (unsigned)(x - m.sx0) < (unsigned)m.ss && (unsigned)(y - m.sy0) < (unsigned)m.ss;
+}
+
+// True if (x, y), 0 <= y < ny, is a cell of the entrance grid: bars of bar x bar
+// cells in columns gx0 .. gx0 + bar - 1, on the rows y >= bar/2 with
+// (y - bar/2) mod (2 bar) < bar (bars and gaps of one height, half gaps at
+// the walls).
+__device__ __forceinline__ bool in_grid(const MemberDev& m, int x, int y) {
+    if ((unsigned)(x - m.gx0) >= (unsigned)m.bar) return false;
+    const int r = y - (m.bar >> 1);
+    return r >= 0 && r % (2 * m.bar) < m.bar;
+}
+
+// True on every solid cell: the square, and the grid of an open channel.
+__device__ __forceinline__ bool in_solid(const MemberDev& m, int x, int y) {
+    return in_square(m, x, y) || in_grid(m, x, y);
 }
 
 // Index of (x, y) in the ring of cells around the square, or -1.

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void mass_partial_kernel(MassArgs a) {
         for (long long e = b0 + threadIdx.x; e < e1; e += 256) {
             const long long cell = e % plane;
             const int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
-            if (!in_square(m, x, y)) acc += (double)base[e];
+            if (!in_solid(m, x, y)) acc += (double)base[e];
         }
     }
     sh[threadIdx.x] = acc;

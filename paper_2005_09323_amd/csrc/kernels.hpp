@@ -34,6 +34,19 @@ struct StepArgs {
     // non-null: the launch covers only these members (all of seg[0]'s shape),
     // tiles_per_member workgroups each, in list order
     const int* active_list;
+    // non-null: open channels; the outlet ghost columns [member][9][ny]
+    // (MemberDev::ghost_off), filled for this step by the ghost kernel
+    const float* ghost;
+};
+
+struct GhostArgs {
+    const MemberDev* members;
+    const int* parity;
+    const int* active;
+    const float* pop0;
+    const float* pop1;
+    float* ghost;
+    int flip;            // parity of the step's source buffer relative to the chunk start
 };
 
 struct InitArgs {
@@ -79,6 +92,8 @@ hipError_t launch_step(int tile_id, const StepArgs& a, int model, hipStream_t st
 // describe strips of 256 columns (tiles_per_member = tiles_x = nx / 256)
 hipError_t launch_step2(int waves, const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, int n_members, long long max_cells, hipStream_t st);
+// the outlet ghost columns of the open-channel members for the next one-step launch
+hipError_t launch_outlet_ghost(const GhostArgs& a, int n_members, int max_ny, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs& a, int n_members, hipStream_t st);
 
 }  // namespace lbm

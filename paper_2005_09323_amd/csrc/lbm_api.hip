@@ -156,15 +156,16 @@ static bool two_step_now(const lbm_ctx* c) {
 
 // Tables of the current tile shape.  A two-step shape applies when every
 // member's width is a multiple of 256 and its block fits 32-bit byte
-// offsets; otherwise (and for the last step of an odd chunk) the library
-// steps with the one-step shape 0, which gives the same results.
+// offsets, and the channels are periodic; otherwise (and for the last step
+// of an odd chunk) the library steps with the one-step shape 0, which gives
+// the same results.
 static int build_segments(lbm_ctx* c) {
     const TileShape ts = TILE_SHAPES[c->tile_id];
     c->two_step = false;
     c->one_tile = c->tile_id;
     if (ts.steps == 2) {
         c->one_tile = 0;
-        bool ok = true;
+        bool ok = !c->open;  // the outlet ghost column is rebuilt between steps
         for (int m = 0; m < c->n; ++m)
             ok = ok && c->desc[m].nx % 256 == 0 && 36LL * c->desc[m].nx * c->desc[m].ny < (1LL << 31);
         if (ok) {
@@ -228,12 +229,19 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
         m.force = d.force_x;
         m.sb = m.s3 = m.s4 = 1.0;
         m.model = 0;
+        m.open = 0;
+        m.gx0 = m.bar = 0;
+        m.sp_x0 = d.nx;
         m.pad_ = 0;
+        m.tau = m.tau_sp = d.tau;
+        m.u_c = 0.0;
+        m.ghost_off = 0;
         m.off = off;
         m.part_off = part;
         off += member_floats(d);
         part += (long long)m.ring * MAX_CHUNK;
         c->max_cells = std::max<long long>(c->max_cells, (long long)d.nx * d.ny);
+        c->max_ny = std::max(c->max_ny, d.ny);
         if (d.nx != members[0].nx || d.ny != members[0].ny) c->uniform_shape = false;
     }
     c->partial_floats = std::max<long long>(part, 1);
@@ -292,6 +300,7 @@ extern "C" int lbm_destroy(lbm_ctx* c) {
     hipFree(c->d_partial);
     hipFree(c->d_scratch);
     hipFree(c->d_iscratch);
+    hipFree(c->d_ghost);
     free_rare_scratch(c);
     delete c;
     return LBM_OK;
@@ -323,6 +332,7 @@ extern "C" int lbm_init_flow(lbm_ctx* c, uint64_t seed, double noise_amp, double
     if (!std::isfinite(noise_amp) || noise_amp < 0 || noise_amp >= 0.5)
         return lbm_fail(LBM_EINVAL, "noise_amp must be in [0, 0.5)");
     if (!std::isfinite(ux0) || std::fabs(ux0) > 0.3) return lbm_fail(LBM_EINVAL, "|ux0| must be <= 0.3");
+    if (c->open && ux0 != 0.0) return lbm_fail(LBM_EINVAL, "an open channel starts from its inlet profile: ux0 must be 0");
     hipError_t e;
     if ((e = fill_int(c->d_parity, c->n, 0, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_cursor, c->n, 0, c->stream)) != hipSuccess ||
@@ -401,6 +411,15 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
     const bool two = two_step_now(c);
     a.active_list = nullptr;
     a2.active_list = nullptr;
+    a.ghost = c->open ? c->d_ghost : nullptr;
+    a2.ghost = nullptr;
+    GhostArgs g;
+    g.members = c->d_members;
+    g.parity = c->d_parity;
+    g.active = c->d_active;
+    g.pop0 = c->pop[0];
+    g.pop1 = c->pop[1];
+    g.ghost = c->d_ghost;
     if (c->n_active == 0) return LBM_OK;  // nothing steps (no drag column either)
     if (c->n_active < c->n && c->uniform_shape) {
         // launch the active members' tiles only: the inactive ones would cost a
@@ -427,6 +446,11 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
         for (; s < chunk; ++s, ++launches) {
             a.slot = s;
             a.flip = launches & 1;
+            if (c->open) {
+                g.flip = a.flip;
+                if ((e = launch_outlet_ghost(g, c->n, c->max_ny, c->stream)) != hipSuccess)
+                    return lbm_hip_fail(e, "outlet ghost kernel");
+            }
             if ((e = launch_step(c->one_tile, a, c->model, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
         }
         if ((e = launch_finalize(finalize_args(c, chunk, 1, launches & 1), c->n, c->stream)) != hipSuccess)
@@ -500,6 +524,63 @@ extern "C" int lbm_set_collision(lbm_ctx* c, int32_t model, double s_bulk, doubl
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "member table upload");
 }
 
+static int validate_open(const lbm_member_desc& d, int i, const lbm_open_channel& o) {
+    if (o.grid_bar > 0) {
+        if (o.grid_x0 < 1 || o.grid_x0 + o.grid_bar > d.nx - 2)
+            return lbm_fail(LBM_EINVAL, "member %d: the grid must lie within columns 1 .. nx - 3", i);
+        if (d.sq_side > 0 && o.grid_x0 + o.grid_bar > d.sq_x0 - 2)
+            return lbm_fail(LBM_EINVAL, "member %d: the grid must end at least two columns before the square", i);
+    }
+    if (d.sq_side > 0 && (d.sq_x0 < 2 || d.sq_x0 + d.sq_side > d.nx - 3))
+        return lbm_fail(LBM_EINVAL, "member %d: an open channel needs two fluid columns before and three after the square", i);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_open_channel(lbm_ctx* c, const lbm_open_channel* oc) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (oc) {
+        if (oc->reserved != 0) return lbm_fail(LBM_EINVAL, "reserved field must be 0");
+        if (!std::isfinite(oc->u_c) || oc->u_c < 0.0 || oc->u_c > 0.3)
+            return lbm_fail(LBM_EINVAL, "inlet centre-line velocity must be in [0, 0.3]");
+        if (oc->grid_bar < 0) return lbm_fail(LBM_EINVAL, "negative grid bar size");
+        if (oc->sponge_x0 < 0) return lbm_fail(LBM_EINVAL, "negative sponge start");
+        if (!(oc->sponge_tau > 0.5) || !std::isfinite(oc->sponge_tau))
+            return lbm_fail(LBM_EINVAL, "sponge relaxation time must be > 1/2");
+        for (int m = 0; m < c->n; ++m) {
+            int rc = validate_open(c->desc[m], m, *oc);
+            if (rc) return rc;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);  // no launch may still read the table or the ghost columns
+    if (e != hipSuccess) return lbm_hip_fail(e, "stream synchronisation");
+    hipFree(c->d_ghost);
+    c->d_ghost = nullptr;
+    long long goff = 0;
+    for (int m = 0; m < c->n; ++m) {
+        MemberDev& md = c->h_members[m];
+        const auto& d = c->desc[m];
+        md.open = oc ? 1 : 0;
+        md.gx0 = oc && oc->grid_bar > 0 ? oc->grid_x0 : 0;
+        md.bar = oc ? oc->grid_bar : 0;
+        md.sp_x0 = oc ? std::min(oc->sponge_x0, d.nx) : d.nx;
+        md.tau_sp = oc ? oc->sponge_tau : d.tau;
+        md.u_c = oc ? oc->u_c : 0.0;
+        md.ghost_off = goff;
+        goff += 9LL * d.ny;
+    }
+    c->open = oc != nullptr;
+    if (c->open && (e = hipMalloc(&c->d_ghost, sizeof(float) * (size_t)goff)) != hipSuccess) {
+        c->open = false;
+        for (auto& md : c->h_members) md.open = md.bar = 0;
+        hipMemcpy(c->d_members, c->h_members.data(), sizeof(MemberDev) * c->n, hipMemcpyHostToDevice);
+        build_segments(c);
+        return lbm_hip_fail(e, "hipMalloc of outlet ghost columns");
+    }
+    e = hipMemcpy(c->d_members, c->h_members.data(), sizeof(MemberDev) * c->n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return lbm_hip_fail(e, "member table upload");
+    return build_segments(c);
+}
+
 extern "C" int32_t lbm_tile_count(void) { return N_TILE_SHAPES; }
 
 extern "C" int lbm_launch_steps(const lbm_ctx* c, int32_t* steps) {
@@ -532,6 +613,14 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
     a.active_list = nullptr;  // every member, whatever the mask
+    a.ghost = c->open ? c->d_ghost : nullptr;
+    GhostArgs g;
+    g.members = c->d_members;
+    g.parity = c->d_parity;
+    g.active = c->d_active;
+    g.pop0 = c->pop[0];
+    g.pop1 = c->pop[1];
+    g.ghost = c->d_ghost;
     // Launches are timed in pairs so every state ends in the buffer it
     // started in; the states do advance (untracked: no drag, no cursor), so
     // callers tune before lbm_init, which rebuilds step 0.
@@ -555,6 +644,11 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         a.slot = 0;
         auto launch = [&](int flip) {
             a.flip = flip;
+            if (c->open) {  // (never two-step)
+                g.flip = flip;
+                hipError_t ge = launch_outlet_ghost(g, c->n, c->max_ny, c->stream);
+                if (ge != hipSuccess) return ge;
+            }
             return two ? launch_step2(ts.tyt, a, c->model, c->stream) : launch_step(t, a, c->model, c->stream);
         };
         // warm-up pair

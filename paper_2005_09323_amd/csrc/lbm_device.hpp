@@ -175,7 +175,9 @@ __device__ __forceinline__ double collide_member(const MemberDev& m, float d[9],
 }
 
 // The nine pulled populations of one cell (x, y) from the state at t, with
-// periodic x, wall rows and the obstacle bouncing back (per-lane gathers).
+// periodic x, wall rows and solid cells bouncing back (per-lane gathers).
+// GRID = false: the square is the only obstacle (periodic channels).
+template <bool GRID = true>
 __device__ __forceinline__ void load_cell(const MemberDev& m, const float* __restrict__ src, int x, int y, float dl[9]) {
     const int nx = m.nx, ny = m.ny;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
@@ -184,11 +186,42 @@ __device__ __forceinline__ void load_cell(const MemberDev& m, const float* __res
         int xs = x - CX[i];
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
         const int ys = y - CY[i];
-        const bool bounce = (ys < 0) | (ys >= ny) | in_square(m, xs, ys);
+        const bool bounce = (ys < 0) | (ys >= ny) | (GRID ? in_solid(m, xs, ys) : in_square(m, xs, ys));
         const unsigned idx = bounce ? (unsigned)OPP[i] * plane + (unsigned)y * (unsigned)nx + (unsigned)x
                                     : (unsigned)i * plane + (unsigned)ys * (unsigned)nx + (unsigned)xs;
         dl[i] = src[idx];
     }
+}
+
+// Solid test of a kernel instantiated for periodic (square only) or open
+// channels (square and grid).
+template <bool OPEN>
+__device__ __forceinline__ bool solid_at(const MemberDev& m, int x, int y) {
+    if constexpr (OPEN) return in_solid(m, x, y);
+    else return in_square(m, x, y);
+}
+
+// Open channel, paper Section 2: the relaxation rates at column x of the
+// sponge zone, tau(x) = tau + (tau_sp - tau) r^2 with
+// r = (x - sp_x0) / (nx - 1 - sp_x0) beyond sp_x0 (tau before it), and the
+// Guo coefficients that depend on them.
+__device__ __forceinline__ void sponge_at(MemberDev& m, int x) {
+    if (x <= m.sp_x0) return;
+    const double r = (double)(x - m.sp_x0) / (double)(m.nx - 1 - m.sp_x0);
+    const double om = 1.0 / (m.tau + ((m.tau_sp - m.tau) * r) * r);
+    m.omega = om;
+    m.gf3 = (1.0 - 0.5 * om) * 3.0 * m.force;
+    m.gf9 = (1.0 - 0.5 * om) * 9.0 * m.force;
+}
+
+// Open channel inlet: the ghost column x = -1 holds the equilibrium of
+// rho = 1, u = (u_in(y), 0), u_in(y) = 4 u_c (y + 1/2)(ny - y - 1/2) / ny^2
+// (zero on the halfway walls).  Its populations with c_ix = +1, the only
+// ones pulled from it, deviate from their rest weights by w_i (3 u + 3 u^2).
+__device__ __forceinline__ float inlet_dev(const MemberDev& m, int i, int y) {
+    const double yc = (double)y + 0.5;
+    const double u = 4.0 * m.u_c * yc * ((double)m.ny - yc) / ((double)m.ny * (double)m.ny);
+    return (float)(WD[i] * (3.0 * u + 3.0 * (u * u)));
 }
 
 // Directions of (x, y) whose next cell lies in the square (x-moving ones only).

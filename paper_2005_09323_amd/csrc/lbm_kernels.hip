@@ -11,26 +11,43 @@
 namespace lbm {
 
 // One fluid-or-solid cell, one population per lane access: used for lattices
-// whose width is not a multiple of 4.
-template <int MODEL>
+// whose width is not a multiple of 4.  OPEN: x is not periodic; populations
+// entering at x = 0 come from the inlet, those entering at x = nx - 1 from
+// the outlet ghost column (ghost: the member's [9][ny] block).
+template <int MODEL, bool OPEN>
 __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
-                                            double* __restrict__ part, int x, int y) {
+                                            double* __restrict__ part, const float* __restrict__ ghost, int x, int y) {
     const int nx = m.nx, ny = m.ny;
     const long long plane = (long long)nx * ny;
-    if (in_square(m, x, y)) return;
+    if (solid_at<OPEN>(m, x, y)) return;
     float dl[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int xs = x - CX[i];
-        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+        if (!OPEN) xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
         const int ys = y - CY[i];
-        const bool bounce = (ys < 0) | (ys >= ny) | in_square(m, xs, ys);
-        const long long idx = bounce ? (long long)OPP[i] * plane + (long long)y * nx + x
-                                     : (long long)i * plane + (long long)ys * nx + xs;
-        dl[i] = src[idx];
+        const bool wall = (ys < 0) | (ys >= ny);
+        const bool inside = (unsigned)xs < (unsigned)nx;
+        const bool bounce = wall || (inside && solid_at<OPEN>(m, xs, ys));
+        if (bounce)
+            dl[i] = src[(long long)OPP[i] * plane + (long long)y * nx + x];
+        else if (OPEN && xs < 0)
+            dl[i] = inlet_dev(m, i, ys);
+        else if (OPEN && xs >= nx)
+            dl[i] = ghost[(long long)i * ny + ys];
+        else
+            dl[i] = src[(long long)i * plane + (long long)ys * nx + xs];
     }
     const int ri = ring_index(m, x, y);
-    const double drag = collide_cell<MODEL>(m, dl, ri >= 0 ? square_links(m, x, y) : 0u);
+    const unsigned links = ri >= 0 ? square_links(m, x, y) : 0u;
+    double drag;
+    if (OPEN) {
+        MemberDev mc = m;
+        sponge_at(mc, x);
+        drag = collide_cell<MODEL>(mc, dl, links);
+    } else {
+        drag = collide_cell<MODEL>(m, dl, links);
+    }
     const long long cell = (long long)y * nx + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = dl[i];
@@ -42,12 +59,15 @@ __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __r
 // pulled from x - 1: the lane's aligned float4 supplies three of its four
 // cells and the fourth comes from the neighbouring lane through a wave
 // shift; the first lane of the wave takes it from one wave-uniform load,
-// which also carries the periodic wrap at x = 0.  Likewise for c_x = -1 at
-// the right end.  Rows next to a wall are wave-uniform (the whole row
-// bounces back); only waves touching the square decide per cell.
-template <int MODEL>
+// which also carries the periodic wrap at x = 0 (OPEN: the inlet's value).
+// Likewise for c_x = -1 at the right end (OPEN: the outlet ghost column).
+// Rows next to a wall are wave-uniform (the whole row bounces back); only
+// waves touching a solid cell decide per cell.  OPEN also sets the
+// relaxation rates per cell (sponge zone).
+template <int MODEL, bool OPEN>
 __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
-                                        double* __restrict__ part, int base, int y, int lane) {
+                                        double* __restrict__ part, const float* __restrict__ ghost, int base, int y,
+                                        int lane) {
     const int nx = m.nx, ny = m.ny;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const int nvalid = min(256, nx - base);  // a multiple of 4
@@ -56,10 +76,12 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
     const int x0 = base + 4 * min(lane, last);
     const unsigned voff = 4u * (unsigned)x0;  // per-lane byte offset within a row
     const unsigned rowoff = (unsigned)y * (unsigned)nx;
-    const int xl = (base == 0 ? nx : base) - 1;
-    const int xr = (base + nvalid == nx) ? 0 : base + nvalid;
+    const bool left_end = base == 0, right_end = base + nvalid == nx;
+    const int xl = (left_end ? nx : base) - 1;
+    const int xr = right_end ? 0 : base + nvalid;
     const bool near_sq = m.ss > 0 && y >= m.sy0 - 1 && y <= m.sy0 + m.ss && base <= m.sx0 + m.ss &&
                          base + nvalid - 1 >= m.sx0 - 1;
+    const bool near = near_sq || (OPEN && m.bar > 0 && base <= m.gx0 + m.bar && base + nvalid - 1 >= m.gx0 - 1);
     // buffer resources over the member's whole block (range-checked by the hardware);
     // row offsets are wave-uniform (scalar), the lane offset is the only vector operand
     const unsigned bytes = 36u * plane;
@@ -79,8 +101,15 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
         v[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * row, BUFFER_NT);
         // the edge element goes through the vector memory pipe like the rest
         // (every lane asks for the same word)
-        e[i] = CX[i] == 1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0))
-                          : (CX[i] == -1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0)) : 0.0f);
+        if (CX[i] == 1) {
+            if (OPEN && left_end) e[i] = wall[i] ? 0.0f : inlet_dev(m, i, ys);
+            else e[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0));
+        } else if (CX[i] == -1) {
+            if (OPEN && right_end) e[i] = ghost[(unsigned)i * (unsigned)ny + (unsigned)(wall[i] ? y : ys)];
+            else e[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0));
+        } else {
+            e[i] = 0.0f;
+        }
     }
     // shift phase: +x movers take x - 1 from the left neighbour lane, -x movers x + 1 from the right
     f4 p[9];
@@ -98,14 +127,14 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
             p[i] = v[i];
         }
     }
-    if (near_sq) {
+    if (near) {
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int ys = y - CY[i];
             if (ys < 0 || ys >= ny) continue;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (in_square(m, x0 + k - CX[i], ys)) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+                if (solid_at<OPEN>(m, x0 + k - CX[i], ys)) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
         }
     }
     // collide the four cells one after the other, in place
@@ -115,20 +144,28 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 #pragma unroll
         for (int i = 0; i < 9; ++i) dl[i] = p[i][k];
         const int ri = (near_sq && live && !in_square(m, x0 + k, y)) ? ring_index(m, x0 + k, y) : -1;
-        const double drag = collide_cell<MODEL>(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
+        const unsigned links = ri >= 0 ? square_links(m, x0 + k, y) : 0u;
+        double drag;
+        if (OPEN) {
+            MemberDev mc = m;
+            sponge_at(mc, x0 + k);
+            drag = collide_cell<MODEL>(mc, dl, links);
+        } else {
+            drag = collide_cell<MODEL>(m, dl, links);
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) p[i][k] = dl[i];
         if (ri >= 0) part[ri] = drag;
     }
     if (!live) return;
-    if (!near_sq) {
+    if (!near) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             __builtin_amdgcn_raw_buffer_store_b128(p[i], rd, voff, 4u * ((unsigned)i * plane + rowoff), BUFFER_NT);
     } else {
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
-            if (in_square(m, x0 + k, y)) continue;
+            if (solid_at<OPEN>(m, x0 + k, y)) continue;
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[(unsigned)i * plane + rowoff + (unsigned)(x0 + k)] = p[i][k];
         }
@@ -139,9 +176,10 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 // TYT waves; a tile is 256 columns by TYT*R rows; wave w handles rows
 // w, w + TYT, ... of the tile.
 // One-row shapes are held to 96 VGPRs (5 waves per SIMD): the memory-bound
-// step needs the waves in flight more than the registers.
-template <int TYT, int R, int MODEL>
-__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 ? 5 : 4))) void step_kernel(StepArgs a) {
+// step needs the waves in flight more than the registers.  OPEN: the
+// open-channel instantiation (inlet, grid, sponge, outlet ghost column).
+template <int TYT, int R, int MODEL, bool OPEN>
+__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 && !OPEN ? 5 : 4))) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec;
     const int mi = block_to_member(a, b, tx, ty, vec);
@@ -153,6 +191,7 @@ __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1
     const float* __restrict__ src = (par ? a.pop1 : a.pop0) + m.off;
     float* __restrict__ dst = (par ? a.pop0 : a.pop1) + m.off;
     double* __restrict__ part = a.partial + m.part_off + (long long)a.slot * m.ring;
+    const float* __restrict__ ghost = OPEN ? a.ghost + m.ghost_off : nullptr;
     const int lane = (int)(threadIdx.x & 63);
     // the wave index is uniform across the wave: say so, so that all row logic stays scalar
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -162,19 +201,92 @@ __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1
         const int y = ty * (TYT * R) + r * TYT + wv;
         if (y >= m.ny) break;
         if (vec) {
-            vec_row<MODEL>(m, src, dst, part, base, y, lane);
+            vec_row<MODEL, OPEN>(m, src, dst, part, ghost, base, y, lane);
         } else {
 #pragma unroll 1
             for (int k = 0; k < 4; ++k) {
                 const int x = base + 64 * k + lane;
-                if (x < m.nx) scalar_cell<MODEL>(m, src, dst, part, x, y);
+                if (x < m.nx) scalar_cell<MODEL, OPEN>(m, src, dst, part, ghost, x, y);
             }
         }
     }
 }
 
+// Open channel outlet (paper Section 2): the ghost column x = nx that the
+// cells of column nx - 1 pull their -x movers from, rebuilt before every
+// step from the post-collision state about to be streamed.  Per row y, with
+// (rho_k, u_k) the density and velocity sum c_i f_i / rho of the stored
+// populations of column k:
+//   rho_g = 1,  u_g = 2 u_{nx-1} - u_{nx-2},
+//   S_xx = ux_{nx-1} - ux_{nx-2},  S_yy = d_y uy_g,
+//   S_xy = (d_y ux_g + uy_{nx-1} - uy_{nx-2}) / 2
+//   (d_y: centred differences over rows, one-sided in the first and last row),
+//   Pi = -2 c_s^2 (tau_out - 1) S with tau_out the outlet column's relaxation time,
+//   g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) : Pi,
+// stored as deviations g_i - w_i in the member's [9][ny] block.  One thread
+// per row; the velocities of the neighbouring rows are recomputed rather
+// than shared.
+struct OutletCol {
+    double ux1, uy1, ux2, uy2;
+};
+
+__device__ __forceinline__ void outlet_velocities(const MemberDev& m, const float* __restrict__ src, int y, OutletCol& o) {
+    const unsigned plane = (unsigned)m.nx * (unsigned)m.ny;
+    for (int c = 0; c < 2; ++c) {
+        const unsigned cell = (unsigned)y * (unsigned)m.nx + (unsigned)(m.nx - 1 - c);
+        double d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = (double)src[(unsigned)i * plane + cell];
+        const double rho = 1.0 + (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8]);
+        const double ux = (((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7])) / rho;
+        const double uy = (((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8])) / rho;
+        if (c == 0) {
+            o.ux1 = ux;
+            o.uy1 = uy;
+        } else {
+            o.ux2 = ux;
+            o.uy2 = uy;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void outlet_ghost_kernel(GhostArgs a) {
+    const int mi = (int)blockIdx.y;
+    const int y = (int)(blockIdx.x * 64 + threadIdx.x);
+    const MemberDev m = a.members[mi];
+    if (!m.open || !a.active[mi] || y >= m.ny) return;
+    const int par = a.parity[mi] ^ a.flip;
+    const float* __restrict__ src = (par ? a.pop1 : a.pop0) + m.off;
+    const int ny = m.ny;
+    const int ya = y > 0 ? y - 1 : 0, yb = y + 1 < ny ? y + 1 : ny - 1;
+    OutletCol c0, ca, cb;
+    outlet_velocities(m, src, y, c0);
+    outlet_velocities(m, src, ya, ca);
+    outlet_velocities(m, src, yb, cb);
+    const double ux = 2.0 * c0.ux1 - c0.ux2, uy = 2.0 * c0.uy1 - c0.uy2;
+    const double uxa = 2.0 * ca.ux1 - ca.ux2, uya = 2.0 * ca.uy1 - ca.uy2;
+    const double uxb = 2.0 * cb.ux1 - cb.ux2, uyb = 2.0 * cb.uy1 - cb.uy2;
+    const double h = (y > 0 && y + 1 < ny) ? 0.5 : 1.0;  // centred or one-sided
+    const double sxx = c0.ux1 - c0.ux2;
+    const double syy = h * (uyb - uya);
+    const double sxy = 0.5 * (h * (uxb - uxa) + (c0.uy1 - c0.uy2));
+    const double tau_out = m.sp_x0 < m.nx - 1 ? m.tau + (m.tau_sp - m.tau) : m.tau;  // tau(nx - 1), r = 1
+    const double cpi = -2.0 * (1.0 / 3.0) * (tau_out - 1.0);  // Pi = cpi * S (rho_g = 1)
+    const double pxx = cpi * sxx, pyy = cpi * syy, pxy = cpi * sxy;
+    const double usq = ux * ux + uy * uy;
+    float* __restrict__ g = a.ghost + m.ghost_off;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double cx = CX[i], cy = CY[i];
+        const double cu = cx * ux + cy * uy;
+        const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
+        g[i * ny + y] = (float)(WD[i] * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+    }
+}
+
 // Step 0: equilibrium with the seeded density and a uniform velocity
-// (u_x0, 0) (at rest for u_x0 = 0), relaxed once.
+// (u_x0, 0) (at rest for u_x0 = 0; an open channel's inlet profile
+// (u_in(y), 0) instead), relaxed once.
 __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const int mi = (int)blockIdx.y;
     const MemberDev m = a.members[mi];
@@ -182,14 +294,19 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
     if (cell >= plane) return;
     const int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
-    if (in_square(m, x, y)) return;
+    if (in_solid(m, x, y)) return;
     double drho = 0.0;
     if (a.noise_amp != 0.0) {
         const U64x4 w = philox4x64_10((uint64_t)cell, (uint64_t)mi, 0, 0, a.seed, PURPOSE_INIT);
         drho = a.noise_amp * (2.0 * uniform53(w.v[0]) - 1.0);
     }
     // f_i = f_i^eq(rho, u0) - w_i = w_i [drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)]
-    const double rho = 1.0 + drho, u0 = a.ux0;
+    double u0 = a.ux0;
+    if (m.open) {
+        const double yc = (double)y + 0.5;
+        u0 = 4.0 * m.u_c * yc * ((double)m.ny - yc) / ((double)m.ny * (double)m.ny);
+    }
+    const double rho = 1.0 + drho;
     float d[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -197,7 +314,9 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         d[i] = (float)(WD[i] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * u0 * u0)));
     }
     const int ri = ring_index(m, x, y);
-    const double drag = collide_member(m, d, ri >= 0 ? square_links(m, x, y) : 0u);
+    MemberDev mc = m;
+    if (m.open) sponge_at(mc, x);
+    const double drag = collide_member(mc, d, ri >= 0 ? square_links(m, x, y) : 0u);
     float* dst = a.pop0 + m.off;  // step 0 lives in buffer 0 (parity 0)
 #pragma unroll
     for (int i = 0; i < 9; ++i) dst[(long long)i * plane + cell] = d[i];
@@ -247,10 +366,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
 
 template <int TYT, int R>
 static hipError_t launch_step_t(const StepArgs& a, int model, hipStream_t st) {
-    if (model == 1)
-        hipLaunchKernelGGL((step_kernel<TYT, R, 1>), dim3(a.total_blocks), dim3(64 * TYT), 0, st, a);
-    else
-        hipLaunchKernelGGL((step_kernel<TYT, R, 0>), dim3(a.total_blocks), dim3(64 * TYT), 0, st, a);
+    const dim3 grid(a.total_blocks), block(64 * TYT);
+    if (a.ghost) {
+        if (model == 1) hipLaunchKernelGGL((step_kernel<TYT, R, 1, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((step_kernel<TYT, R, 0, true>), grid, block, 0, st, a);
+    } else {
+        if (model == 1) hipLaunchKernelGGL((step_kernel<TYT, R, 1, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((step_kernel<TYT, R, 0, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -281,6 +404,11 @@ hipError_t launch_step(int tile_id, const StepArgs& a, int model, hipStream_t st
         case 7: return launch_step_t<8, 2>(a, model, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_outlet_ghost(const GhostArgs& a, int n_members, int max_ny, hipStream_t st) {
+    hipLaunchKernelGGL(outlet_ghost_kernel, dim3((max_ny + 63) / 64, n_members), dim3(64), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const InitArgs& a, int n_members, long long max_cells, hipStream_t st) {

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         float hv[9];
         f4 p[9];
         if (row_a) {
-            load_cell(m, src, xh, y, hv);
+            load_cell<false>(m, src, xh, y, hv);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int ys = y - CY[i];

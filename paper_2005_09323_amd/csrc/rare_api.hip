@@ -78,7 +78,11 @@ static int run_gather(lbm_ctx* c, double eps, const float* snapshots, int n_snap
         sa.scale = r.scale;
         sa.coef_w = r.coef_w;
         const lbm_member_desc& d0 = c->desc[0];
-        sa.n_fluid = (double)d0.nx * d0.ny - (double)d0.sq_side * d0.sq_side;
+        const MemberDev& m0 = c->h_members[0];
+        long long grid_cells = 0;  // an open channel's grid bars (same rule as in_grid)
+        for (int y = m0.bar / 2; m0.bar > 0 && y < d0.ny; ++y)
+            if ((y - m0.bar / 2) % (2 * m0.bar) < m0.bar) grid_cells += m0.bar;
+        sa.n_fluid = (double)d0.nx * d0.ny - (double)d0.sq_side * d0.sq_side - (double)grid_cells;
         sa.eps = eps;
         sa.n = c->n;
         sa.n_snap = n_snap;

@@ -104,6 +104,15 @@ class Ensemble:
         code = {"bgk": 0, "central": 1}[model]
         native.check(self.lib.lbm_set_collision(self._ctx, code, s_bulk, s_third, s_fourth))
 
+    def set_open_channel(self, u_c: Optional[float], grid_x0: int = 0, grid_bar: int = 0,
+                         sponge_x0: int = 1 << 30, sponge_tau: float = 1.0) -> None:
+        """Inlet, entrance grid, sponge and outlet instead of periodic x (None: periodic); before init."""
+        if u_c is None:
+            native.check(self.lib.lbm_set_open_channel(self._ctx, None))
+            return
+        oc = native.OpenChannelDesc(u_c, grid_x0, grid_bar, sponge_x0, 0, sponge_tau)
+        native.check(self.lib.lbm_set_open_channel(self._ctx, ctypes.byref(oc)))
+
     def launch_steps(self) -> int:
         """Lattice steps per launch of the shape in use (2 for the two-step kernel)."""
         n = ctypes.c_int32()

@@ -35,6 +35,11 @@ class MemberDesc(ctypes.Structure):
                 ("tau", ctypes.c_double), ("force_x", ctypes.c_double)]
 
 
+class OpenChannelDesc(ctypes.Structure):
+    _fields_ = [("u_c", ctypes.c_double), ("grid_x0", ctypes.c_int32), ("grid_bar", ctypes.c_int32),
+                ("sponge_x0", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sponge_tau", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _U64 = ctypes.c_uint64
@@ -58,6 +63,7 @@ _SIG = {
     "lbm_face_diagnostics": (ctypes.c_int, [_P, _P]),
     "lbm_set_collision": (ctypes.c_int, [_P, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_launch_steps": (ctypes.c_int, [_P, ctypes.POINTER(_I)]),
+    "lbm_set_open_channel": (ctypes.c_int, [_P, _P]),
     "lbm_autotune": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),
     "gktl_select_clone": (ctypes.c_int, [_P, _D, _U64, _I, _D, _P, _I, _P, _P]),
     "lbm_perturb": (ctypes.c_int, [_P, _P, _U64, _I, _D, _P, _I]),

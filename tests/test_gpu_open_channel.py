@@ -1,0 +1,162 @@
+"""GPU parity of the open channel (inlet, entrance grid, sponge, outlet) against the FP64 oracle.
+
+The HIP path runs through the C ABI (lbm_set_open_channel); the oracle is
+``oracle.open_channel`` started from the same state (the inlet profile at
+every x with the seeded density).  Tolerances as for the periodic channel:
+drag series max-norm relative error <= 1e-5, populations <= 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lbm as olbm
+from oracle.open_channel import OpenChannel, inlet_velocity
+
+pytestmark = pytest.mark.gpu
+
+CM_RATES = (1.0, 1.0, 1.0)
+
+
+def _ensemble(members, cap, op, collision=None, tile=None):
+    from paper_2005_09323_amd.ensemble import Ensemble
+    ens = Ensemble(members, series_capacity=cap)
+    if tile is not None:
+        ens.set_tile(tile)
+    if collision is not None:
+        ens.set_collision("central", *collision)
+    ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau)
+    return ens
+
+
+def _channel(m, op, collision=None):
+    return olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square, collision,
+                        open=OpenChannel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau))
+
+
+def _oracle(m, op, seed, member_index, amp, steps, collision=None):
+    ch = _channel(m, op, collision)
+    rho = olbm.init_density(ch, seed, member_index, amp)
+    u = np.repeat(inlet_velocity(ch)[:, None], ch.nx, axis=1)
+    f0 = olbm.equilibrium(rho, u, np.zeros_like(u))
+    f0[:, olbm.solid_mask(ch)] = 0.0
+    fout, drags = olbm.run(ch, f0, steps)
+    return ch, fout, drags
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# a 4-aligned width (row kernel) and a ragged one (per-cell kernel); grid, square and sponge in both
+MEMBERS = [workloads.Member(192, 48, 0.56, 0.0, (70, 19, 8)),
+           workloads.Member(130, 40, 0.6, 2e-6, (50, 16, 6))]
+OPEN = workloads.OpenParams(0.05, 12, 6, 150 - 40, 0.95)  # sponge over the last ~40 / ~20 columns
+
+
+@pytest.mark.parametrize("collision", [None, CM_RATES])
+def test_open_channel_against_oracle(collision):
+    steps = 1000
+    ens = _ensemble(MEMBERS, steps, OPEN, collision)
+    assert ens.launch_steps() == 1
+    ens.init(31, 1e-3)
+    ens.step(steps - 1)
+    torch.cuda.synchronize()
+    drag = ens.drag(0, steps).cpu().numpy()
+    states = [ens.state(i).double().cpu().numpy() for i in range(len(MEMBERS))]
+    assert int(ens.flags().sum()) == 0
+    ens.close()
+    for i, m in enumerate(MEMBERS):
+        ch, fout, ref = _oracle(m, OPEN, 31, i, 1e-3, steps, collision)
+        fluid = ~olbm.solid_mask(ch)
+        e_drag = _rel(drag[i], ref)
+        e_late = _rel(drag[i][200:], ref[200:])  # after the start-up pressure wave (drag ~50x larger)
+        e_state = _rel(states[i][:, fluid], (fout - olbm.W[:, None, None])[:, fluid])
+        print(f"member {i} collision {collision}: drag rel err {e_drag:.2e} (after step 200: {e_late:.2e}), "
+              f"state rel err {e_state:.2e}")
+        assert e_drag <= 1e-5 and e_late <= 1e-5, (i, e_drag, e_late)
+        assert e_state <= 1e-4, (i, e_state)
+
+
+def test_open_channel_tiles_bit_identical():
+    """Every one-step launch shape gives the same states and drag; two-step shapes fall back to one step."""
+    from paper_2005_09323_amd import native
+    steps = 120
+    runs = []
+    for tile in list(range(16)) + [16, 20]:
+        ens = _ensemble(MEMBERS, steps, OPEN, tile=tile)
+        assert ens.launch_steps() == 1
+        ens.init(5, 1e-3)
+        ens.step(steps - 1)
+        torch.cuda.synchronize()
+        runs.append((ens.drag(0, steps).cpu().numpy(), [ens.state(i).cpu().numpy().copy() for i in range(2)]))
+        ens.close()
+    assert native.lib().lbm_tile_count() == 21
+    d0, s0 = runs[0]
+    for i, m in enumerate(MEMBERS):
+        fluid = ~olbm.solid_mask(_channel(m, OPEN))
+        for d, s in runs[1:]:
+            assert np.array_equal(d[i], d0[i])
+            assert np.array_equal(s[i][:, fluid], s0[i][:, fluid])
+
+
+def test_open_channel_inactive_members_frozen():
+    """Members masked off keep their state and time while the others step through the ghost kernel."""
+    steps = 60
+    ens = _ensemble(MEMBERS[:1] * 3, steps, OPEN)
+    ens.init(9, 1e-3)
+    ens.step(9)
+    frozen = ens.state(1).cpu().numpy().copy()
+    ens.set_active([1, 0, 1])
+    ens.step(20)
+    torch.cuda.synchronize()
+    assert np.array_equal(ens.state(1).cpu().numpy(), frozen)
+    assert [ens.time(i) for i in range(3)] == [30, 10, 30]
+    ens.close()
+
+
+def test_paper_open_channel_sampled_members():
+    """The paper's channel (512 x 128, R = 16, grid of R/2 bars, sponge), central moments, the
+    full 1024-member ensemble in the launch configuration of the benchmark: two sampled members
+    against the oracle over 200 steps."""
+    wl = workloads.open_channel()
+    op, rates = wl.extra["open"], wl.extra["rates"]
+    steps = 200
+    ens = _ensemble(wl.members, steps, op, rates)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(steps - 1)
+    torch.cuda.synchronize()
+    sample = (0, 777)
+    drag = ens.drag(0, steps).cpu().numpy()[list(sample)]
+    assert int(ens.flags().sum()) == 0
+    ens.close()
+    torch.cuda.empty_cache()
+    for k, i in enumerate(sample):
+        _, _, ref = _oracle(wl.members[i], op, wl.seed, i, wl.noise_amp, steps, rates)
+        assert _rel(drag[k], ref) <= 1e-5, (i, _rel(drag[k], ref))
+
+
+def test_open_channel_argument_errors():
+    from paper_2005_09323_amd.native import LbmError
+    m = workloads.Member(192, 48, 0.56, 0.0, (70, 19, 8))
+    bad = [workloads.OpenParams(0.05, 61, 8, 150, 0.9),    # grid ends next to the square's front cells
+           workloads.OpenParams(0.05, 0, 6, 150, 0.9),     # grid on the inlet column
+           workloads.OpenParams(-0.01, 12, 6, 150, 0.9),   # negative inlet velocity
+           workloads.OpenParams(0.05, 12, 6, 150, 0.5)]    # sponge tau not above 1/2
+    from paper_2005_09323_amd.ensemble import Ensemble
+    ens = Ensemble([m], series_capacity=10)
+    for op in bad:
+        with pytest.raises(LbmError):
+            ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau)
+    ens.close()
+    near_outlet = workloads.Member(192, 48, 0.56, 0.0, (182, 19, 8))  # square within 3 columns of the outlet
+    ens = Ensemble([near_outlet], series_capacity=10)
+    with pytest.raises(LbmError):
+        ens.set_open_channel(0.05)
+    ens.close()
+    ens = _ensemble([m], 10, OPEN)
+    with pytest.raises(LbmError):
+        ens.init(1, 0.0, ux0=0.02)  # an open channel starts from its inlet profile
+    ens.set_open_channel(None)      # back to periodic: a uniform start is allowed again
+    ens.init(1, 0.0, ux0=0.02)
+    ens.close()

@@ -106,6 +106,27 @@ def mixed_sizes(per_size: int = 64, steps: int = 20_000, seed: int = 5) -> Workl
     return Workload(f"mixed {per_size}x(256x64,512x128,1024x256)", members, steps, seed=seed)
 
 
+@dataclass(frozen=True)
+class OpenParams:
+    """Open channel: inlet centre-line velocity, grid bars (first column, size; 0 = none),
+    sponge (last column before the ramp, relaxation time at the outlet)."""
+    u_c: float
+    grid_x0: int
+    bar: int
+    sponge_x0: int
+    sponge_tau: float
+
+
+def open_channel(n_members: int = 1024) -> Workload:
+    """The paper's flow (Section 2): 512 x 128 cells (513 x 129 mesh points), square R = 16 at
+    the centre, entrance grid of bars R/2 from x = 32, inlet centre-line velocity 0.05, sponge over
+    the last 64 columns rising to tau 1; tau 0.501 (Re_grid = u_c R/2 / nu = 1200), no body
+    force; meant for the central-moment collision with unit higher-order rates."""
+    m = Member(512, 128, 0.501, 0.0, centred_square(256, 64, 16))
+    return Workload(f"open channel {n_members}x512x128", [m] * n_members, 2000, seed=300,
+                    extra=dict(open=OpenParams(0.05, 32, 8, 447, 1.0), rates=(1.0, 1.0, 1.0)))
+
+
 # ----------------------------------------------------------------------------
 # seeded inputs the method does not draw itself
 
