@@ -217,7 +217,8 @@ int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third
  * Requirements (every member): grid within columns 1 .. nx - 3 and, with a
  * square, ending at least two columns before it; the square at least two
  * columns from the inlet (sq_x0 >= 2) and three from the outlet
- * (sq_x0 + s <= nx - 3); 0 <= u_c <= 0.3; sponge_tau > 1/2.  The body
+ * (sq_x0 + s <= nx - 3); 0 <= u_c <= 0.3; sponge_tau > 1/2; ny <= 2048
+ * (LBM_EUNSUPPORTED beyond: the ghost kernel keeps a column in LDS).  The body
  * force of the members still applies.  Open channels step one lattice step
  * per launch (the ghost column is rebuilt between steps) plus one small
  * launch per step for the ghost columns.  lbm_init then starts every member

@@ -88,14 +88,18 @@ __device__ __forceinline__ bool in_square(const MemberDev& m, int x, int y) {
     return (unsigned)(x - m.sx0) < (unsigned)m.ss && (unsigned)(y - m.sy0) < (unsigned)m.ss;
 }
 
-// True if (x, y), 0 <= y < ny, is a cell of the entrance grid: bars of bar x bar
-// cells in columns gx0 .. gx0 + bar - 1, on the rows y >= bar/2 with
-// (y - bar/2) mod (2 bar) < bar (bars and gaps of one height, half gaps at
-// the walls).
-__device__ __forceinline__ bool in_grid(const MemberDev& m, int x, int y) {
-    if ((unsigned)(x - m.gx0) >= (unsigned)m.bar) return false;
+// True if row y, 0 <= y < ny, crosses the bars of the entrance grid: rows
+// y >= bar/2 with (y - bar/2) mod (2 bar) < bar (bars and gaps of one height,
+// half gaps at the walls).
+__device__ __forceinline__ bool grid_row(const MemberDev& m, int y) {
     const int r = y - (m.bar >> 1);
-    return r >= 0 && r % (2 * m.bar) < m.bar;
+    return m.bar > 0 && r >= 0 && r % (2 * m.bar) < m.bar;
+}
+
+// True if (x, y), 0 <= y < ny, is a cell of the entrance grid: bar x bar cells
+// in columns gx0 .. gx0 + bar - 1 on the grid's rows.
+__device__ __forceinline__ bool in_grid(const MemberDev& m, int x, int y) {
+    return (unsigned)(x - m.gx0) < (unsigned)m.bar && grid_row(m, y);
 }
 
 // True on every solid cell: the square, and the grid of an open channel.

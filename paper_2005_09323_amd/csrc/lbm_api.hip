@@ -525,6 +525,7 @@ extern "C" int lbm_set_collision(lbm_ctx* c, int32_t model, double s_bulk, doubl
 }
 
 static int validate_open(const lbm_member_desc& d, int i, const lbm_open_channel& o) {
+    if (d.ny > 2048) return lbm_fail(LBM_EUNSUPPORTED, "member %d: open channels support ny <= 2048", i);
     if (o.grid_bar > 0) {
         if (o.grid_x0 < 1 || o.grid_x0 + o.grid_bar > d.nx - 2)
             return lbm_fail(LBM_EINVAL, "member %d: the grid must lie within columns 1 .. nx - 3", i);

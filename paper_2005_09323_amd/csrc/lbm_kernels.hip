@@ -81,7 +81,19 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
     const int xr = right_end ? 0 : base + nvalid;
     const bool near_sq = m.ss > 0 && y >= m.sy0 - 1 && y <= m.sy0 + m.ss && base <= m.sx0 + m.ss &&
                          base + nvalid - 1 >= m.sx0 - 1;
-    const bool near = near_sq || (OPEN && m.bar > 0 && base <= m.gx0 + m.bar && base + nvalid - 1 >= m.gx0 - 1);
+    // which of the rows y - 1, y, y + 1 cross the grid's bars (wave-uniform)
+    bool grow[3] = {false, false, false};
+    if (OPEN) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) grow[j] = y - 1 + j >= 0 && y - 1 + j < ny && grid_row(m, y - 1 + j);
+    }
+    const bool near_grid = OPEN && (grow[0] || grow[1] || grow[2]) && base <= m.gx0 + m.bar &&
+                           base + nvalid - 1 >= m.gx0 - 1;
+    const bool near = near_sq || near_grid;
+    // solid test of column xx in row y - 1 + j
+    auto solid = [&](int xx, int j) {
+        return in_square(m, xx, y - 1 + j) || (OPEN && grow[j] && (unsigned)(xx - m.gx0) < (unsigned)m.bar);
+    };
     // buffer resources over the member's whole block (range-checked by the hardware);
     // row offsets are wave-uniform (scalar), the lane offset is the only vector operand
     const unsigned bytes = 36u * plane;
@@ -134,7 +146,7 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
             if (ys < 0 || ys >= ny) continue;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (solid_at<OPEN>(m, x0 + k - CX[i], ys)) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+                if (solid(x0 + k - CX[i], 1 - CY[i])) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
         }
     }
     // collide the four cells one after the other, in place
@@ -158,14 +170,20 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
         if (ri >= 0) part[ri] = drag;
     }
     if (!live) return;
-    if (!near) {
+    // lanes whose four cells are all fluid store 16 bytes at a time; the few
+    // holding a solid cell store cell by cell and leave it untouched
+    bool any_solid = false;
+    if (near)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) any_solid |= solid(x0 + k, 1);
+    if (!any_solid) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             __builtin_amdgcn_raw_buffer_store_b128(p[i], rd, voff, 4u * ((unsigned)i * plane + rowoff), BUFFER_NT);
     } else {
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
-            if (solid_at<OPEN>(m, x0 + k, y)) continue;
+            if (solid(x0 + k, 1)) continue;
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[(unsigned)i * plane + rowoff + (unsigned)(x0 + k)] = p[i][k];
         }
@@ -179,7 +197,7 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 // step needs the waves in flight more than the registers.  OPEN: the
 // open-channel instantiation (inlet, grid, sponge, outlet ghost column).
 template <int TYT, int R, int MODEL, bool OPEN>
-__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 && !OPEN ? 5 : 4))) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 && !OPEN ? 5 : (OPEN && MODEL == 1 ? 3 : 4)))) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec;
     const int mi = block_to_member(a, b, tx, ty, vec);
@@ -223,64 +241,64 @@ __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1
 //   (d_y: centred differences over rows, one-sided in the first and last row),
 //   Pi = -2 c_s^2 (tau_out - 1) S with tau_out the outlet column's relaxation time,
 //   g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) : Pi,
-// stored as deviations g_i - w_i in the member's [9][ny] block.  One thread
-// per row; the velocities of the neighbouring rows are recomputed rather
-// than shared.
-struct OutletCol {
-    double ux1, uy1, ux2, uy2;
-};
-
-__device__ __forceinline__ void outlet_velocities(const MemberDev& m, const float* __restrict__ src, int y, OutletCol& o) {
-    const unsigned plane = (unsigned)m.nx * (unsigned)m.ny;
-    for (int c = 0; c < 2; ++c) {
-        const unsigned cell = (unsigned)y * (unsigned)m.nx + (unsigned)(m.nx - 1 - c);
-        double d[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = (double)src[(unsigned)i * plane + cell];
-        const double rho = 1.0 + (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8]);
-        const double ux = (((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7])) / rho;
-        const double uy = (((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8])) / rho;
-        if (c == 0) {
-            o.ux1 = ux;
-            o.uy1 = uy;
-        } else {
-            o.ux2 = ux;
-            o.uy2 = uy;
-        }
-    }
-}
-
-__global__ __launch_bounds__(64) void outlet_ghost_kernel(GhostArgs a) {
-    const int mi = (int)blockIdx.y;
-    const int y = (int)(blockIdx.x * 64 + threadIdx.x);
+// stored as deviations g_i - w_i in the member's [9][ny] block.
+// One workgroup per member: each thread takes rows t, t + 256, ... and puts
+// the velocities of the last two columns into LDS ([4][ny] doubles); after a
+// barrier every thread rebuilds the ghost populations of its rows from its
+// own and its neighbours' entries.
+__global__ __launch_bounds__(256) void outlet_ghost_kernel(GhostArgs a) {
+    const int mi = (int)blockIdx.x;
     const MemberDev m = a.members[mi];
-    if (!m.open || !a.active[mi] || y >= m.ny) return;
+    if (!m.open || !a.active[mi]) return;  // the whole workgroup
+    extern __shared__ double vel[];        // ux1[ny], uy1[ny], ux2[ny], uy2[ny]
     const int par = a.parity[mi] ^ a.flip;
     const float* __restrict__ src = (par ? a.pop1 : a.pop0) + m.off;
-    const int ny = m.ny;
-    const int ya = y > 0 ? y - 1 : 0, yb = y + 1 < ny ? y + 1 : ny - 1;
-    OutletCol c0, ca, cb;
-    outlet_velocities(m, src, y, c0);
-    outlet_velocities(m, src, ya, ca);
-    outlet_velocities(m, src, yb, cb);
-    const double ux = 2.0 * c0.ux1 - c0.ux2, uy = 2.0 * c0.uy1 - c0.uy2;
-    const double uxa = 2.0 * ca.ux1 - ca.ux2, uya = 2.0 * ca.uy1 - ca.uy2;
-    const double uxb = 2.0 * cb.ux1 - cb.ux2, uyb = 2.0 * cb.uy1 - cb.uy2;
-    const double h = (y > 0 && y + 1 < ny) ? 0.5 : 1.0;  // centred or one-sided
-    const double sxx = c0.ux1 - c0.ux2;
-    const double syy = h * (uyb - uya);
-    const double sxy = 0.5 * (h * (uxb - uxa) + (c0.uy1 - c0.uy2));
-    const double tau_out = m.sp_x0 < m.nx - 1 ? m.tau + (m.tau_sp - m.tau) : m.tau;  // tau(nx - 1), r = 1
-    const double cpi = -2.0 * (1.0 / 3.0) * (tau_out - 1.0);  // Pi = cpi * S (rho_g = 1)
-    const double pxx = cpi * sxx, pyy = cpi * syy, pxy = cpi * sxy;
-    const double usq = ux * ux + uy * uy;
-    float* __restrict__ g = a.ghost + m.ghost_off;
+    const int nx = m.nx, ny = m.ny;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    for (int y = (int)threadIdx.x; y < ny; y += 256) {
+        float d1[9], d2[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const double cx = CX[i], cy = CY[i];
-        const double cu = cx * ux + cy * uy;
-        const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
-        g[i * ny + y] = (float)(WD[i] * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+        for (int i = 0; i < 9; ++i) {
+            const unsigned row = (unsigned)i * plane + (unsigned)y * (unsigned)nx;
+            d1[i] = src[row + (unsigned)(nx - 1)];
+            d2[i] = src[row + (unsigned)(nx - 2)];
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            double d[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = (double)(c == 0 ? d1[i] : d2[i]);
+            const double rho = 1.0 + (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8]);
+            vel[(2 * c) * ny + y] = (((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7])) / rho;
+            vel[(2 * c + 1) * ny + y] = (((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8])) / rho;
+        }
+    }
+    __syncthreads();
+    const double* ux1 = vel;
+    const double* uy1 = vel + ny;
+    const double* ux2 = vel + 2 * ny;
+    const double* uy2 = vel + 3 * ny;
+    const double tau_out = m.sp_x0 < nx - 1 ? m.tau + (m.tau_sp - m.tau) : m.tau;  // tau(nx - 1), r = 1
+    const double cpi = -2.0 * (1.0 / 3.0) * (tau_out - 1.0);                      // Pi = cpi * S (rho_g = 1)
+    float* __restrict__ g = a.ghost + m.ghost_off;
+    for (int y = (int)threadIdx.x; y < ny; y += 256) {
+        const int ya = y > 0 ? y - 1 : 0, yb = y + 1 < ny ? y + 1 : ny - 1;
+        const double h = (y > 0 && y + 1 < ny) ? 0.5 : 1.0;  // centred or one-sided
+        const double ux = 2.0 * ux1[y] - ux2[y], uy = 2.0 * uy1[y] - uy2[y];
+        const double uxa = 2.0 * ux1[ya] - ux2[ya], uya = 2.0 * uy1[ya] - uy2[ya];
+        const double uxb = 2.0 * ux1[yb] - ux2[yb], uyb = 2.0 * uy1[yb] - uy2[yb];
+        const double sxx = ux1[y] - ux2[y];
+        const double syy = h * (uyb - uya);
+        const double sxy = 0.5 * (h * (uxb - uxa) + (uy1[y] - uy2[y]));
+        const double pxx = cpi * sxx, pyy = cpi * syy, pxy = cpi * sxy;
+        const double usq = ux * ux + uy * uy;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double cx = CX[i], cy = CY[i];
+            const double cu = cx * ux + cy * uy;
+            const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
+            g[i * ny + y] = (float)(WD[i] * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+        }
     }
 }
 
@@ -407,7 +425,7 @@ hipError_t launch_step(int tile_id, const StepArgs& a, int model, hipStream_t st
 }
 
 hipError_t launch_outlet_ghost(const GhostArgs& a, int n_members, int max_ny, hipStream_t st) {
-    hipLaunchKernelGGL(outlet_ghost_kernel, dim3((max_ny + 63) / 64, n_members), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(outlet_ghost_kernel, dim3(n_members), dim3(256), sizeof(double) * 4 * max_ny, st, a);
     return hipGetLastError();
 }
 
