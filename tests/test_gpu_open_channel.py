@@ -160,3 +160,44 @@ def test_open_channel_argument_errors():
     ens.set_open_channel(None)      # back to periodic: a uniform start is allowed again
     ens.init(1, 0.0, ux0=0.02)
     ens.close()
+
+
+def test_perturbation_on_open_channel_matches_oracle():
+    """Appendix-D perturbation with the mass rescale on open-channel members: the grid's bars
+    are solid and stay out of every mass sum, as the square does."""
+    from oracle import perturb as opert
+    m = workloads.Member(64, 24, 0.56, 0.0, (30, 8, 4))
+    op = workloads.OpenParams(0.05, 6, 4, 50, 0.9)
+    ch = _channel(m, op)
+    fluid = ~olbm.solid_mask(ch)
+    assert (~fluid).sum() > 16  # the grid's bars are there
+
+    def state(seed, steps):
+        _, fout, _ = _oracle(m, op, seed, 0, 1e-2, steps)
+        d = (fout - olbm.W[:, None, None]).astype(np.float32)
+        d[:, ~fluid] = 0.0
+        return d
+
+    def full(d):
+        f = d.astype(np.float64) + olbm.W[:, None, None]
+        f[:, ~fluid] = 0.0
+        return f
+
+    n, n_snap, eps, key, period = 4, 3, 0.01, 8, 11
+    states = [state(300 + i, 3) for i in range(n)]
+    snaps = np.stack([state(400 + q, 5) for q in range(n_snap)])
+    ens = _ensemble([m] * n, 64, op)
+    ens.init(0, 0.0)
+    for i in range(n):
+        ens.copy_state_in(i, torch.from_numpy(states[i]).cuda(), 1)
+    ens.perturb([0, 1, 0, 1], key, period, eps, torch.from_numpy(snaps).cuda())
+    snaps_full = np.stack([full(snaps[q]) for q in range(n_snap)])
+    for i in range(n):
+        gpu = ens.state(i).double().cpu().numpy()[:, fluid]
+        if i in (0, 2):
+            assert np.array_equal(gpu, states[i][:, fluid].astype(np.float64))
+        else:
+            exp = opert.perturb(full(states[i]), snaps_full, opert.alphas(key, i, period, n_snap), eps, fluid)
+            ref = (exp - olbm.W[:, None, None])[:, fluid]
+            assert np.abs(gpu - ref).max() / np.abs(ref).max() <= 1e-6, i
+    ens.close()
