@@ -79,6 +79,7 @@ struct MemberDev {
     int pad_;
     double tau;           // relaxation time outside the sponge
     double tau_sp;        // relaxation time at the outlet column
+    double sp_inv;        // 1 / (nx - 1 - sp_x0) (0: no sponge)
     double u_c;           // inlet centre-line velocity
     long long ghost_off;  // first float of the member's outlet ghost column [9][ny]
 };

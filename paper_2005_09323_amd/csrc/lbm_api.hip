@@ -234,6 +234,7 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
         m.sp_x0 = d.nx;
         m.pad_ = 0;
         m.tau = m.tau_sp = d.tau;
+        m.sp_inv = 0.0;
         m.u_c = 0.0;
         m.ghost_off = 0;
         m.off = off;
@@ -565,6 +566,7 @@ extern "C" int lbm_set_open_channel(lbm_ctx* c, const lbm_open_channel* oc) {
         md.bar = oc ? oc->grid_bar : 0;
         md.sp_x0 = oc ? std::min(oc->sponge_x0, d.nx) : d.nx;
         md.tau_sp = oc ? oc->sponge_tau : d.tau;
+        md.sp_inv = md.sp_x0 < d.nx - 1 ? 1.0 / (double)(d.nx - 1 - md.sp_x0) : 0.0;
         md.u_c = oc ? oc->u_c : 0.0;
         md.ghost_off = goff;
         goff += 9LL * d.ny;

@@ -12,8 +12,9 @@ namespace lbm {
 
 // One fluid-or-solid cell, one population per lane access: used for lattices
 // whose width is not a multiple of 4.  OPEN: x is not periodic; populations
-// entering at x = 0 come from the inlet, those entering at x = nx - 1 from
-// the outlet ghost column (ghost: the member's [9][ny] block).
+// entering at x = 0 come from the inlet ghost column, those entering at
+// x = nx - 1 from the outlet ghost column (ghost: the member's [9][ny] block,
+// +x movers from the inlet, -x movers from the outlet).
 template <int MODEL, bool OPEN>
 __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __restrict__ src, float* __restrict__ dst,
                                             double* __restrict__ part, const float* __restrict__ ghost, int x, int y) {
@@ -31,9 +32,7 @@ __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __r
         const bool bounce = wall || (inside && solid_at<OPEN>(m, xs, ys));
         if (bounce)
             dl[i] = src[(long long)OPP[i] * plane + (long long)y * nx + x];
-        else if (OPEN && xs < 0)
-            dl[i] = inlet_dev(m, i, ys);
-        else if (OPEN && xs >= nx)
+        else if (OPEN && (xs < 0 || xs >= nx))
             dl[i] = ghost[(long long)i * ny + ys];
         else
             dl[i] = src[(long long)i * plane + (long long)ys * nx + xs];
@@ -59,8 +58,9 @@ __device__ __forceinline__ void scalar_cell(const MemberDev& m, const float* __r
 // pulled from x - 1: the lane's aligned float4 supplies three of its four
 // cells and the fourth comes from the neighbouring lane through a wave
 // shift; the first lane of the wave takes it from one wave-uniform load,
-// which also carries the periodic wrap at x = 0 (OPEN: the inlet's value).
-// Likewise for c_x = -1 at the right end (OPEN: the outlet ghost column).
+// which also carries the periodic wrap at x = 0 (OPEN: the inlet ghost
+// column).  Likewise for c_x = -1 at the right end (OPEN: the outlet ghost
+// column).
 // Rows next to a wall are wave-uniform (the whole row bounces back); only
 // waves touching a solid cell decide per cell.  OPEN also sets the
 // relaxation rates per cell (sponge zone).
@@ -90,10 +90,17 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
     const bool near_grid = OPEN && (grow[0] || grow[1] || grow[2]) && base <= m.gx0 + m.bar &&
                            base + nvalid - 1 >= m.gx0 - 1;
     const bool near = near_sq || near_grid;
-    // solid test of column xx in row y - 1 + j
-    auto solid = [&](int xx, int j) {
-        return in_square(m, xx, y - 1 + j) || (OPEN && grow[j] && (unsigned)(xx - m.gx0) < (unsigned)m.bar);
+    // bit j: column x0 - 1 + j (j = 0..5, the lane's cells and their neighbours) holds grid bars
+    unsigned gcols = 0;
+    if (near_grid)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) gcols |= ((unsigned)(x0 - 1 + j - m.gx0) < (unsigned)m.bar ? 1u : 0u) << j;
+    // solid test of column x0 + dx (dx = -1 .. 4) in row y - 1 + j
+    auto solid = [&](int dx, int j) {
+        return (near_sq && in_square(m, x0 + dx, y - 1 + j)) || (OPEN && grow[j] && ((gcols >> (dx + 1)) & 1u));
     };
+    // open channel: the columns of this segment reach the sponge zone (wave-uniform)
+    const bool sponge_wave = OPEN && base + nvalid - 1 > m.sp_x0;
     // buffer resources over the member's whole block (range-checked by the hardware);
     // row offsets are wave-uniform (scalar), the lane offset is the only vector operand
     const unsigned bytes = 36u * plane;
@@ -114,7 +121,7 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
         // the edge element goes through the vector memory pipe like the rest
         // (every lane asks for the same word)
         if (CX[i] == 1) {
-            if (OPEN && left_end) e[i] = wall[i] ? 0.0f : inlet_dev(m, i, ys);
+            if (OPEN && left_end) e[i] = ghost[(unsigned)i * (unsigned)ny + (unsigned)(wall[i] ? y : ys)];
             else e[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0));
         } else if (CX[i] == -1) {
             if (OPEN && right_end) e[i] = ghost[(unsigned)i * (unsigned)ny + (unsigned)(wall[i] ? y : ys)];
@@ -141,12 +148,14 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
     }
     if (near) {
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const int ys = y - CY[i];
-            if (ys < 0 || ys >= ny) continue;
+        for (int k = 0; k < 4; ++k) {
+            if (solid(k, 1)) continue;  // a solid cell's results are never stored
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (solid(x0 + k - CX[i], 1 - CY[i])) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+            for (int i = 1; i < 9; ++i) {
+                const int ys = y - CY[i];
+                if (ys < 0 || ys >= ny) continue;
+                if (solid(k - CX[i], 1 - CY[i])) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+            }
         }
     }
     // collide the four cells one after the other, in place
@@ -160,7 +169,7 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
         double drag;
         if (OPEN) {
             MemberDev mc = m;
-            sponge_at(mc, x0 + k);
+            if (sponge_wave) sponge_at(mc, x0 + k);
             drag = collide_cell<MODEL>(mc, dl, links);
         } else {
             drag = collide_cell<MODEL>(m, dl, links);
@@ -170,20 +179,21 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
         if (ri >= 0) part[ri] = drag;
     }
     if (!live) return;
-    // lanes whose four cells are all fluid store 16 bytes at a time; the few
-    // holding a solid cell store cell by cell and leave it untouched
-    bool any_solid = false;
+    // lanes whose four cells are all fluid store 16 bytes at a time, lanes
+    // with only solid cells store nothing, and the rare mixed ones store cell
+    // by cell, leaving the solid cells untouched
+    unsigned smask = 0;  // bit k: cell x0 + k is solid
     if (near)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) any_solid |= solid(x0 + k, 1);
-    if (!any_solid) {
+        for (int k = 0; k < 4; ++k) smask |= (solid(k, 1) ? 1u : 0u) << k;
+    if (smask == 0) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             __builtin_amdgcn_raw_buffer_store_b128(p[i], rd, voff, 4u * ((unsigned)i * plane + rowoff), BUFFER_NT);
-    } else {
+    } else if (smask != 0xFu) {
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
-            if (solid(x0 + k, 1)) continue;
+            if (solid(k, 1)) continue;
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[(unsigned)i * plane + rowoff + (unsigned)(x0 + k)] = p[i][k];
         }
@@ -197,7 +207,7 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 // step needs the waves in flight more than the registers.  OPEN: the
 // open-channel instantiation (inlet, grid, sponge, outlet ghost column).
 template <int TYT, int R, int MODEL, bool OPEN>
-__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 && !OPEN ? 5 : (OPEN && MODEL == 1 ? 3 : 4)))) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 && !OPEN ? 5 : 4))) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec;
     const int mi = block_to_member(a, b, tx, ty, vec);
@@ -230,9 +240,12 @@ __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1
     }
 }
 
-// Open channel outlet (paper Section 2): the ghost column x = nx that the
-// cells of column nx - 1 pull their -x movers from, rebuilt before every
-// step from the post-collision state about to be streamed.  Per row y, with
+// Open channel boundaries (paper Section 2), rebuilt before every step into
+// the member's [9][ny] ghost block: the +x movers (i = 1, 5, 8) of the inlet
+// column x = -1, which the cells of column 0 pull, and the -x movers
+// (i = 3, 6, 7) of the outlet column x = nx, which the cells of column nx - 1
+// pull.  The inlet is the equilibrium of the parabolic profile (inlet_dev).
+// The outlet comes from the post-collision state about to be streamed.  Per row y, with
 // (rho_k, u_k) the density and velocity sum c_i f_i / rho of the stored
 // populations of column k:
 //   rho_g = 1,  u_g = 2 u_{nx-1} - u_{nx-2},
@@ -294,10 +307,14 @@ __global__ __launch_bounds__(256) void outlet_ghost_kernel(GhostArgs a) {
         const double usq = ux * ux + uy * uy;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const double cx = CX[i], cy = CY[i];
-            const double cu = cx * ux + cy * uy;
-            const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
-            g[i * ny + y] = (float)(WD[i] * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+            if (CX[i] == 1) {
+                g[i * ny + y] = inlet_dev(m, i, y);
+            } else if (CX[i] == -1) {
+                const double cx = CX[i], cy = CY[i];
+                const double cu = cx * ux + cy * uy;
+                const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
+                g[i * ny + y] = (float)(WD[i] * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+            }
         }
     }
 }
