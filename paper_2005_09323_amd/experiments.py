@@ -94,19 +94,29 @@ class DragStats:
     sigma_window: dict = field(default_factory=dict)   # window -> std of the window mean
 
 
+def _autocorrelation(d: np.ndarray) -> np.ndarray:
+    """Autocorrelation of the member-centred series d [members, steps], averaged over members,
+    lags 0 .. steps/2 - 1 (zero-padded FFT, normalised to 1 at lag 0)."""
+    steps = d.shape[1]
+    dd = d - d.mean(axis=1, keepdims=True)
+    acf = np.zeros(steps // 2)
+    for row in dd:
+        f = np.fft.rfft(row, 2 * steps)
+        acf += np.fft.irfft(f * np.conj(f))[: steps // 2]
+    return acf / acf[0]
+
+
+def _first_zero(acf: np.ndarray) -> int:
+    return int(np.argmax(acf < 0)) if (acf < 0).any() else len(acf)
+
+
 def drag_stats(ens: Ensemble, steps: int, windows) -> DragStats:
     """Run `steps` steps and measure the drag statistics (host FP64 analysis of the series)."""
     ens.set_time(1)
     ens.step(steps)
     d = ens.drag(1, 1 + steps).double().cpu().numpy()
     mu, sigma = float(d.mean()), float(d.std())
-    dd = d - d.mean(axis=1, keepdims=True)
-    acf = np.zeros(steps // 2)
-    for row in dd:
-        f = np.fft.rfft(row, 2 * steps)
-        acf += np.fft.irfft(f * np.conj(f))[: steps // 2]
-    acf /= acf[0]
-    tau_c = int(np.argmax(acf < 0)) if (acf < 0).any() else steps // 2
+    tau_c = _first_zero(_autocorrelation(d))
     sw = {}
     for w in windows:
         c = np.cumsum(np.pad(d, ((0, 0), (1, 0))), axis=1)
@@ -352,9 +362,72 @@ def ams_compare(flow: Flow, n: int, repeats: int, out=None, seed: int = 200, win
     src.close()
 
 
+@dataclass
+class OpenFlow:
+    """The paper's flow (Section 2): 512 x 128 cells, square R = 16 at the centre, entrance grid
+    of bars R/2 from x = 32, parabolic inlet of centre-line velocity 0.05, sponge over the last
+    64 columns rising to tau 1, tau 0.501 (Re_grid = u_c (R/2) / nu = 1200), central moments."""
+    nx: int = 512
+    ny: int = 128
+    tau: float = 0.501
+    square: tuple = (248, 56, 16)
+    u_c: float = 0.05
+    grid_x0: int = 32
+    bar: int = 8
+    sponge_x0: int = 447
+    sponge_tau: float = 1.0
+    rates: tuple = (1.0, 1.0, 1.0)
+
+
+def open_channel_stats(flow: OpenFlow, n: int, burn: int, steps: int, out=None, seed: int = 300):
+    """Drag statistics of the paper's open channel against what the paper reports for it
+    (Section 3): the correlation time tau_c (first zero of the drag autocorrelation) is about
+    4 turnover times T0 = R/U, i.e. T0/tau_c, read as a Strouhal number, about 0.25, and the
+    drag distribution is skewed to the right (exponential right tail).  U is the inlet's
+    centre-line velocity; T0 with the bulk velocity (2/3 of it) is given too."""
+    t0 = _sync_time()
+    cap = min(burn, 50_000) + 2
+    ens = Ensemble([Member(flow.nx, flow.ny, flow.tau, 0.0, flow.square)] * n,
+                   series_capacity=max(cap, steps + 2))
+    ens.set_collision("central", *flow.rates)
+    ens.set_open_channel(flow.u_c, flow.grid_x0, flow.bar, flow.sponge_x0, flow.sponge_tau)
+    ens.init(seed, 1e-3)
+    done = 0
+    while done < burn:
+        chunk = min(cap - 2, burn - done)
+        ens.set_time(1)
+        ens.step(chunk)
+        done += chunk
+        _progress(f"open channel burn-in {n} members: {done}/{burn} steps")
+    ens.set_time(1)
+    ens.step(steps)
+    d = ens.drag(1, 1 + steps).double().cpu().numpy()
+    bad = int(ens.flags().sum().item())
+    ens.close()
+    wall = _sync_time() - t0
+    acf = _autocorrelation(d)
+    tau_c = _first_zero(acf)
+    z = (d - d.mean()) / d.std()
+    R = flow.square[2]
+    t0_c, t0_b = R / flow.u_c, R / (2.0 / 3.0 * flow.u_c)
+    half = steps // 2
+    rec = {"experiment": "open_channel_stats", "members": n, "burn_steps": burn, "steps": steps,
+           "nonfinite_members": bad, "wall_s": round(wall, 1),
+           "drag_mean": float(d.mean()), "drag_std": float(d.std()),
+           "drag_mean_first_half": float(d[:, :half].mean()), "drag_mean_second_half": float(d[:, half:].mean()),
+           "drag_coefficient_centreline": float(d.mean() / (0.5 * flow.u_c ** 2 * R)),
+           "skewness": float((z ** 3).mean()), "excess_kurtosis": float((z ** 4).mean() - 3.0),
+           "tau_c_steps": tau_c, "T0_centreline_steps": t0_c, "T0_bulk_steps": t0_b,
+           "tau_c_over_T0_centreline": tau_c / t0_c, "tau_c_over_T0_bulk": tau_c / t0_b,
+           "strouhal_T0_over_tau_c_centreline": t0_c / tau_c, "strouhal_T0_over_tau_c_bulk": t0_b / tau_c,
+           "paper": {"tau_c_over_T0": 4.0, "strouhal": 0.25}}
+    _emit(out, rec)
+    return rec
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["gktl", "ams", "all"])
+    ap.add_argument("which", choices=["gktl", "ams", "all", "open"])
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--repeats", type=int, default=10)
     ap.add_argument("--burn", type=int, default=Flow.burn)
@@ -366,6 +439,8 @@ def main(argv=None):
     ap.add_argument("--clone-tc", type=float, default=1.0, help="GKTL cloning period in correlation times")
     ap.add_argument("--ta-windows", type=int, default=2, help="GKTL trajectory length T_a in windows T")
     ap.add_argument("--ks", default="0.25,0.5,1")
+    ap.add_argument("--open-burn", type=int, default=60_000, help="open channel: burn-in steps")
+    ap.add_argument("--open-steps", type=int, default=60_000, help="open channel: measured steps")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
@@ -377,6 +452,8 @@ def main(argv=None):
     if args.which in ("ams", "all"):
         ams_compare(flow, args.ams_n, args.repeats, out=args.out, rounds=args.rounds, eps=args.eps,
                     z=args.ams_z, direct_steps=args.direct_steps)
+    if args.which == "open":
+        open_channel_stats(OpenFlow(), args.n, args.open_burn, args.open_steps, out=args.out)
 
 
 if __name__ == "__main__":

@@ -25,3 +25,15 @@ def test_rel_scatter():
     assert abs(out[0] - np.std([1.0, 3.0], ddof=1) / 2.0) < 1e-15
     assert out[1] == 0.0
     assert math.isinf(out[2])
+
+
+def test_autocorrelation_first_zero_of_a_sine():
+    """A sine of period P decorrelates at lag P/4 (the autocorrelation of a long sine is cos)."""
+    import numpy as np
+    from paper_2005_09323_amd.experiments import _autocorrelation, _first_zero
+    P = 400
+    t = np.arange(40 * P)
+    d = np.stack([np.sin(2 * np.pi * t / P + ph) for ph in (0.0, 1.0, 2.0)])
+    acf = _autocorrelation(d)
+    assert abs(acf[0] - 1) < 1e-12
+    assert abs(_first_zero(acf) - P / 4) <= 1
