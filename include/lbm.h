@@ -14,7 +14,8 @@
  *   (0,0), (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1);
  *   weights 4/9, 1/9 (x4), 1/36 (x4).
  * - Geometry: ny fluid rows between halfway bounce-back walls at y = 0 and
- *   y = ny, periodic in x.  The square with side s and lower-left cell
+ *   y = ny, periodic in x (or fed by an inlet and drained by an outlet,
+ *   lbm_set_open_channel).  The square with side s and lower-left cell
  *   (sq_x0, sq_y0) is solid on cells sq_x0..sq_x0+s-1, sq_y0..sq_y0+s-1 and
  *   must keep one fluid cell to every side: 1 <= sq_x0, sq_x0 + s <= nx - 1,
  *   1 <= sq_y0, sq_y0 + s <= ny - 1.  s = 0 means no obstacle.
@@ -23,7 +24,8 @@
  *   starting at the sum of 9*nx*ny over members 0..m-1, laid out
  *   [i][y][x] with x fastest.  What is stored for step t is the
  *   post-collision state f_i^out(t); streaming happens when step t+1 reads
- *   it.  Solid cells are never read or written.
+ *   it.  Solid cells (the square, an open channel's grid bars) are never
+ *   written by the lattice steps, and what they hold never enters a result.
  * - Time: lbm_init produces step 0 (equilibrium at rest with the seeded
  *   density, relaxed once) and its drag; each step of lbm_step_batch
  *   produces the next step and its drag.  The drag of step t is written at
