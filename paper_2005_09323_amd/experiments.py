@@ -38,6 +38,12 @@ class Flow:
     u0: float = 0.02
     burn: int = 200_000
 
+    def ensemble(self, n: int, cap: int) -> "Ensemble":
+        return Ensemble([Member(self.nx, self.ny, self.tau, self.force_x, self.square)] * n, series_capacity=cap)
+
+    def start(self, ens: "Ensemble", seed: int) -> None:
+        ens.init(seed, 1e-3, ux0=self.u0)
+
 
 @dataclass
 class Member:
@@ -46,10 +52,6 @@ class Member:
     tau: float
     force_x: float
     square: tuple
-
-
-def _member(f: Flow) -> Member:
-    return Member(f.nx, f.ny, f.tau, f.force_x, f.square)
 
 
 def _sync_time() -> float:
@@ -71,8 +73,8 @@ def _emit(out, rec: dict) -> None:
 
 def burn_in(flow: Flow, n: int, seed: int, cap: int) -> Ensemble:
     """n members from independent seeded noise, run to the statistically stationary state."""
-    ens = Ensemble([_member(flow)] * n, series_capacity=cap)
-    ens.init(seed, 1e-3, ux0=flow.u0)
+    ens = flow.ensemble(n, cap)
+    flow.start(ens, seed)
     done = 0
     while done < flow.burn:
         chunk = min(cap - 2, flow.burn - done)
@@ -198,7 +200,7 @@ def gktl_and_direct(flow: Flow, n: int, repeats: int, ks, out=None, seed: int = 
                 "rel_err_binomial": [math.sqrt((1 - p) / (n_blocks * p)) if p > 0 else None for p in p_dir],
                 "s_per_member_step": step_cost, "wall_s_to_10pct": dir_wall10})
     snaps = _snapshots(src, 10)
-    g = Ensemble([_member(flow)] * n, series_capacity=t_a + 2)
+    g = flow.ensemble(n, t_a + 2)
     extra = [1 if m >= n_src else 0 for m in range(n)]
     for ki, k in enumerate(ks):
         p_all, walls, lams, roots = [], [], [], []
@@ -324,7 +326,7 @@ def ams_compare(flow: Flow, n: int, repeats: int, out=None, seed: int = 200, win
     snaps = _snapshots(src, 10)
     for name, use_net in (("plain", None), ("learned", net)):
         probs, walls, costs, iters, extinct = [], [], [], [], 0
-        ens = Ensemble([_member(flow)] * n, series_capacity=t_a + 2)
+        ens = flow.ensemble(n, t_a + 2)
         for rep in range(repeats):
             src.set_time(1)
             src.step(2 * st.tau_c)
@@ -377,6 +379,16 @@ class OpenFlow:
     sponge_x0: int = 447
     sponge_tau: float = 1.0
     rates: tuple = (1.0, 1.0, 1.0)
+    burn: int = 60_000
+
+    def ensemble(self, n: int, cap: int) -> Ensemble:
+        ens = Ensemble([Member(self.nx, self.ny, self.tau, 0.0, self.square)] * n, series_capacity=cap)
+        ens.set_collision("central", *self.rates)
+        ens.set_open_channel(self.u_c, self.grid_x0, self.bar, self.sponge_x0, self.sponge_tau)
+        return ens
+
+    def start(self, ens: Ensemble, seed: int) -> None:
+        ens.init(seed, 1e-3)
 
 
 def open_channel_stats(flow: OpenFlow, n: int, burn: int, steps: int, out=None, seed: int = 300):
@@ -387,11 +399,8 @@ def open_channel_stats(flow: OpenFlow, n: int, burn: int, steps: int, out=None, 
     centre-line velocity; T0 with the bulk velocity (2/3 of it) is given too."""
     t0 = _sync_time()
     cap = min(burn, 50_000) + 2
-    ens = Ensemble([Member(flow.nx, flow.ny, flow.tau, 0.0, flow.square)] * n,
-                   series_capacity=max(cap, steps + 2))
-    ens.set_collision("central", *flow.rates)
-    ens.set_open_channel(flow.u_c, flow.grid_x0, flow.bar, flow.sponge_x0, flow.sponge_tau)
-    ens.init(seed, 1e-3)
+    ens = flow.ensemble(n, max(cap, steps + 2))
+    flow.start(ens, seed)
     done = 0
     while done < burn:
         chunk = min(cap - 2, burn - done)
@@ -430,7 +439,9 @@ def main(argv=None):
     ap.add_argument("which", choices=["gktl", "ams", "all", "open"])
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--repeats", type=int, default=10)
-    ap.add_argument("--burn", type=int, default=Flow.burn)
+    ap.add_argument("--flow", choices=["channel", "open"], default="channel",
+                    help="channel: periodic force-driven channel; open: the paper's open channel (gktl, open)")
+    ap.add_argument("--burn", type=int, default=None, help="burn-in steps (default: the flow's)")
     ap.add_argument("--rounds", type=int, default=200)
     ap.add_argument("--ams-n", type=int, default=256)
     ap.add_argument("--ams-z", type=float, default=5.0, help="AMS level in window standard deviations")
@@ -444,12 +455,16 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    flow = Flow(burn=args.burn)
+    flow = Flow() if args.flow == "channel" else OpenFlow()
+    if args.burn is not None:
+        flow.burn = args.burn
     if args.which in ("gktl", "all"):
         gktl_and_direct(flow, args.n, args.repeats, ks=[float(k) for k in args.ks.split(",")],
                         out=args.out, direct_steps=args.direct_steps, eps=args.eps, clone_tc=args.clone_tc,
                         ta_windows=args.ta_windows)
     if args.which in ("ams", "all"):
+        if args.flow != "channel":
+            raise SystemExit("the AMS comparison runs on the periodic channel")
         ams_compare(flow, args.ams_n, args.repeats, out=args.out, rounds=args.rounds, eps=args.eps,
                     z=args.ams_z, direct_steps=args.direct_steps)
     if args.which == "open":
