@@ -201,3 +201,58 @@ def test_perturbation_on_open_channel_matches_oracle():
             ref = (exp - olbm.W[:, None, None])[:, fluid]
             assert np.abs(gpu - ref).max() / np.abs(ref).max() <= 1e-6, i
     ens.close()
+
+
+def test_gktl_run_on_open_channel_matches_oracle():
+    """A GKTL run (selection, cloning, lineage rebuild, reweighted tail probability) on open-channel
+    members: the ghost columns of every step come from the cloned states.  Oracle: its GKTL driving
+    its open channel from the same seeded initial states."""
+    import math
+
+    from oracle import gktl as ogktl
+    from paper_2005_09323_amd import rare
+    m = workloads.Member(64, 24, 0.56, 0.0, (30, 8, 4))
+    op = workloads.OpenParams(0.05, 6, 4, 50, 0.9)
+    ch = _channel(m, op)
+    n, tau, n_per, k, key, seed = 8, 16, 4, 0.5, 9, 31
+    mu, sigma, dt, window = 0.0, 0.05, 1.0 / 16, 8
+    ens = _ensemble([m] * n, n_per * tau + 1, op)
+    ens.init(seed, 1e-2)
+    ens.set_observable(mu, sigma, dt)
+    run = rare.run_gktl(ens, k, n_per, tau, key)
+    tr = rare.rebuild(run, ens)
+    fmax = rare.window_maxima(tr.series, window)
+
+    u = np.repeat(inlet_velocity(ch)[:, None], ch.nx, axis=1)
+
+    def start(i):
+        f0 = olbm.equilibrium(olbm.init_density(ch, seed, i, 1e-2), u, np.zeros_like(u))
+        f0[:, olbm.solid_mask(ch)] = 0.0
+        return olbm.collide(ch, f0)
+
+    x0 = np.stack([start(i) for i in range(n)])
+
+    def advance(x, period):
+        x = x.copy()
+        samples = np.empty((n, tau))
+        integ = np.empty(n)
+        for j in range(n):
+            fo = x[j]
+            for s in range(tau):
+                fo = olbm.collide(ch, olbm.stream(ch, fo))
+                samples[j, s] = olbm.drag(ch, fo)
+            x[j] = fo
+            integ[j] = math.fsum(((samples[j] - mu) / sigma * dt).tolist())
+        return x, samples, integ
+
+    res = ogktl.run(x0, advance, n_per, k, key)
+    assert np.array_equal(run.ancestors.cpu().numpy(), np.stack(res["ancestors"]))
+    ref_series = ogktl.reconstruct_series(res["samples"], res["ancestors"])
+    gpu_series = tr.series.double().cpu().numpy()
+    assert np.abs(gpu_series - ref_series).max() <= 1e-5 * np.abs(ref_series).max()
+    lin = ogktl.lineage(res["ancestors"])
+    ref_int = sum(res["integrals"][i][lin[:, i]] for i in range(n_per))
+    assert np.allclose(tr.integral.cpu().numpy(), ref_int, rtol=1e-5, atol=1e-6)
+    ref_fmax = ogktl.window_mean_max(ref_series, window)
+    assert np.allclose(fmax.cpu().numpy(), ref_fmax, rtol=1e-5)
+    ens.close()
