@@ -168,6 +168,22 @@ def legs():
                         "mfma_TFLOPs_train": round(256 * flop_train / (t_train / 1e3) / 1e12, 3),
                         "mfma_TFLOPs_forward": round(256 * flop_fwd / (t_fwd / 1e3) / 1e12, 3)}
     del net, xt, lt
+    # launch-bound batches (an AMS branch re-simulates a handful of members): full 64-step chunks
+    # replayed from a captured HIP graph against launching every kernel of every chunk
+    m = workloads.ams_ensemble().members[0]
+    small = {}
+    for graphs in (True, False):
+        ens = Ensemble([m] * 16, series_capacity=1100)
+        ens.set_graphs(graphs)
+        ens.init(1, 1e-3)
+        ens.step(64)
+        torch.cuda.synchronize()
+        small["graphs" if graphs else "launches"] = _timed(lambda: ens.step(1024)) / 1024
+        ens.close()
+    out["small_batch"] = {"workload": "16 x 512x128 (AMS branch size)", "ms_per_step_graphs": round(small["graphs"], 5),
+                          "ms_per_step_launches": round(small["launches"], 5),
+                          "MLUPS_graphs": round(16 * m.cells / small["graphs"] / 1e3, 1),
+                          "MLUPS_launches": round(16 * m.cells / small["launches"] / 1e3, 1)}
     # the paper's open channel (inlet, grid, sponge, outlet ghost column), central moments:
     # one step per launch plus the small ghost-column launch
     wl = workloads.open_channel()

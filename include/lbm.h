@@ -137,9 +137,18 @@ int lbm_set_active(lbm_ctx* ctx, const int32_t* active_host);
  * then collide), recording each step's drag in the member's next column and
  * adding (f_d - mu)/sigma * dt to accum.  A member whose drag becomes
  * non-finite is flagged (lbm_flags).  LBM_ERANGE if an active member would
- * pass series_capacity.
+ * pass series_capacity.  Steps are grouped in chunks of 64 (one drag
+ * reduction each); a full chunk is captured once into a HIP graph (on a
+ * private stream) and replayed on the context's stream until the launch
+ * configuration changes (tile shape, collision, open channel, number of
+ * active members, observable), so that the host submits one graph per 64
+ * steps instead of up to 65 launches.
  */
 int lbm_step_batch(lbm_ctx* ctx, int32_t n_steps);
+
+/* Replay captured chunks in lbm_step_batch (on = 1, the default) or launch
+   every kernel of every chunk (on = 0).  Both give bit-identical results. */
+int lbm_set_graphs(lbm_ctx* ctx, int32_t on);
 
 /* Copy drag columns [t0, t1) of every member into out_dev (device float[n][t1-t0]). */
 int lbm_drag(const lbm_ctx* ctx, int32_t t0, int32_t t1, float* out_dev);

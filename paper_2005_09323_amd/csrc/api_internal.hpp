@@ -34,6 +34,21 @@ struct RareScratch {
     int* status_host = nullptr;
 };
 
+// What a captured chunk of lbm_step_batch depends on besides device memory:
+// a replay is valid while all of it is unchanged.
+struct ChunkGraphKey {
+    int tile_id, one_tile, two, waves2, model, open, chunk;
+    int total_blocks, total_blocks2, compact;
+    double mu, inv_sigma_dt;
+    const void* ghost;
+    bool operator==(const ChunkGraphKey& o) const {
+        return tile_id == o.tile_id && one_tile == o.one_tile && two == o.two && waves2 == o.waves2 &&
+               model == o.model && open == o.open && chunk == o.chunk && total_blocks == o.total_blocks &&
+               total_blocks2 == o.total_blocks2 && compact == o.compact && mu == o.mu &&
+               inv_sigma_dt == o.inv_sigma_dt && ghost == o.ghost;
+    }
+};
+
 struct lbm_ctx {
     int n = 0;
     std::vector<lbm_member_desc> desc;
@@ -80,9 +95,18 @@ struct lbm_ctx {
     int total_blocks2 = 0;
     lbm::Segment seg2[lbm::MAX_SEGMENTS];
     RareScratch rare;
+    // full chunks of lbm_step_batch replay one captured HIP graph (captured on
+    // a private stream, launched on `stream`)
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    ChunkGraphKey graph_key{};
+    int graph_launches = 0;  // launches in the captured chunk (its parity swaps the buffers)
 };
 
 void free_rare_scratch(lbm_ctx* c);
+void free_chunk_graph(lbm_ctx* c);
 
 int lbm_fail(int code, const char* fmt, ...);
 int lbm_hip_fail(hipError_t e, const char* what);

@@ -302,6 +302,8 @@ extern "C" int lbm_destroy(lbm_ctx* c) {
     hipFree(c->d_scratch);
     hipFree(c->d_iscratch);
     hipFree(c->d_ghost);
+    free_chunk_graph(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     free_rare_scratch(c);
     delete c;
     return LBM_OK;
@@ -432,30 +434,66 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
             a2.total_blocks = c->n_active * c->seg2[0].tiles_per_member;
         }
     }
-    hipError_t e;
-    int done = 0;
-    while (done < n_steps) {
-        const int chunk = std::min(n_steps - done, c->chunk);
-        // every launch swaps the buffers once, whether it makes one step or two
-        int launches = 0, s = 0;
+    // the launches of one chunk of steps on stream st; `launches` counts them
+    // (every launch swaps the buffers once, whether it makes one step or two)
+    auto enqueue = [&](int chunk, hipStream_t st, int& launches) -> hipError_t {
+        hipError_t e;
+        int s = 0;
+        launches = 0;
         if (two)
             for (; s + 1 < chunk; s += 2, ++launches) {
                 a2.slot = s;
                 a2.flip = launches & 1;
-                if ((e = launch_step2(waves2, a2, c->model, c->stream)) != hipSuccess) return lbm_hip_fail(e, "two-step kernel");
+                if ((e = launch_step2(waves2, a2, c->model, st)) != hipSuccess) return e;
             }
         for (; s < chunk; ++s, ++launches) {
             a.slot = s;
             a.flip = launches & 1;
             if (c->open) {
                 g.flip = a.flip;
-                if ((e = launch_outlet_ghost(g, c->n, c->max_ny, c->stream)) != hipSuccess)
-                    return lbm_hip_fail(e, "outlet ghost kernel");
+                if ((e = launch_outlet_ghost(g, c->n, c->max_ny, st)) != hipSuccess) return e;
             }
-            if ((e = launch_step(c->one_tile, a, c->model, c->stream)) != hipSuccess) return lbm_hip_fail(e, "step kernel");
+            if ((e = launch_step(c->one_tile, a, c->model, st)) != hipSuccess) return e;
         }
-        if ((e = launch_finalize(finalize_args(c, chunk, 1, launches & 1), c->n, c->stream)) != hipSuccess)
-            return lbm_hip_fail(e, "drag reduction");
+        return launch_finalize(finalize_args(c, chunk, 1, launches & 1), c->n, st);
+    };
+    hipError_t e;
+    int done = 0;
+    while (done < n_steps) {
+        const int chunk = std::min(n_steps - done, c->chunk);
+        int launches = 0;
+        if (c->graphs && chunk == c->chunk) {
+            ChunkGraphKey key{c->tile_id, c->one_tile, two ? 1 : 0, waves2, c->model, c->open ? 1 : 0, chunk,
+                              a.total_blocks, a2.total_blocks, a.active_list ? 1 : 0, c->mu, c->dt / c->sigma,
+                              (const void*)c->d_ghost};
+            if (!c->graph_exec || !(key == c->graph_key)) {
+                free_chunk_graph(c);
+                if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+                    return lbm_hip_fail(e, "capture stream");
+                if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                    return lbm_hip_fail(e, "begin capture");
+                int l = 0;
+                const hipError_t ce = enqueue(chunk, c->cap_stream, l);
+                hipGraph_t gr = nullptr;
+                const hipError_t ee = hipStreamEndCapture(c->cap_stream, &gr);
+                if (ce != hipSuccess || ee != hipSuccess) {
+                    if (gr) hipGraphDestroy(gr);
+                    return lbm_hip_fail(ce != hipSuccess ? ce : ee, "capture of a chunk of steps");
+                }
+                if ((e = hipGraphInstantiateWithFlags(&c->graph_exec, gr, 0)) != hipSuccess) {
+                    hipGraphDestroy(gr);
+                    c->graph_exec = nullptr;
+                    return lbm_hip_fail(e, "graph instantiation");
+                }
+                c->graph = gr;
+                c->graph_key = key;
+                c->graph_launches = l;
+            }
+            if ((e = hipGraphLaunch(c->graph_exec, c->stream)) != hipSuccess) return lbm_hip_fail(e, "graph launch");
+            launches = c->graph_launches;
+        } else if ((e = enqueue(chunk, c->stream, launches)) != hipSuccess) {
+            return lbm_hip_fail(e, "lattice step launches");
+        }
         for (int m = 0; m < c->n; ++m)
             if (c->h_active[m]) {
                 c->h_parity[m] ^= (launches & 1);
@@ -463,6 +501,19 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
             }
         done += chunk;
     }
+    return LBM_OK;
+}
+
+void free_chunk_graph(lbm_ctx* c) {
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+extern "C" int lbm_set_graphs(lbm_ctx* c, int32_t on) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    c->graphs = on != 0;
     return LBM_OK;
 }
 
@@ -555,6 +606,7 @@ extern "C" int lbm_set_open_channel(lbm_ctx* c, const lbm_open_channel* oc) {
     }
     hipError_t e = hipStreamSynchronize(c->stream);  // no launch may still read the table or the ghost columns
     if (e != hipSuccess) return lbm_hip_fail(e, "stream synchronisation");
+    free_chunk_graph(c);  // it holds the old ghost pointer
     hipFree(c->d_ghost);
     c->d_ghost = nullptr;
     long long goff = 0;

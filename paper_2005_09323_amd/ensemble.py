@@ -113,6 +113,10 @@ class Ensemble:
         oc = native.OpenChannelDesc(u_c, grid_x0, grid_bar, sponge_x0, 0, sponge_tau)
         native.check(self.lib.lbm_set_open_channel(self._ctx, ctypes.byref(oc)))
 
+    def set_graphs(self, on: bool) -> None:
+        """Replay full 64-step chunks from a captured HIP graph (default) or launch every kernel."""
+        native.check(self.lib.lbm_set_graphs(self._ctx, 1 if on else 0))
+
     def launch_steps(self) -> int:
         """Lattice steps per launch of the shape in use (2 for the two-step kernel)."""
         n = ctypes.c_int32()

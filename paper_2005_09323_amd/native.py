@@ -64,6 +64,7 @@ _SIG = {
     "lbm_set_collision": (ctypes.c_int, [_P, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_launch_steps": (ctypes.c_int, [_P, ctypes.POINTER(_I)]),
     "lbm_set_open_channel": (ctypes.c_int, [_P, _P]),
+    "lbm_set_graphs": (ctypes.c_int, [_P, _I]),
     "lbm_autotune": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),
     "gktl_select_clone": (ctypes.c_int, [_P, _D, _U64, _I, _D, _P, _I, _P, _P]),
     "lbm_perturb": (ctypes.c_int, [_P, _P, _U64, _I, _D, _P, _I]),
