@@ -142,7 +142,7 @@ int lbm_set_active(lbm_ctx* ctx, const int32_t* active_host);
  * private stream) and replayed on the context's stream until the launch
  * configuration changes (tile shape, collision, open channel, number of
  * active members, observable), so that the host submits one graph per 64
- * steps instead of up to 65 launches.
+ * steps instead of 33 to 129 kernel launches.
  */
 int lbm_step_batch(lbm_ctx* ctx, int32_t n_steps);
 
