@@ -52,12 +52,13 @@ def _rel(a, b):
 MEMBERS = [workloads.Member(192, 48, 0.56, 0.0, (70, 19, 8)),
            workloads.Member(130, 40, 0.6, 2e-6, (50, 16, 6))]
 OPEN = workloads.OpenParams(0.05, 12, 6, 150 - 40, 0.95)  # sponge over the last ~40 / ~20 columns
+OPEN_ODD = workloads.OpenParams(0.04, 9, 5, 100, 0.8)      # odd bar (half gap of 2 rows), longer sponge
 
 
-@pytest.mark.parametrize("collision", [None, CM_RATES])
-def test_open_channel_against_oracle(collision):
+@pytest.mark.parametrize("collision,op", [(None, OPEN), (CM_RATES, OPEN), (None, OPEN_ODD)])
+def test_open_channel_against_oracle(collision, op):
     steps = 1000
-    ens = _ensemble(MEMBERS, steps, OPEN, collision)
+    ens = _ensemble(MEMBERS, steps, op, collision)
     assert ens.launch_steps() == 1
     ens.init(31, 1e-3)
     ens.step(steps - 1)
@@ -67,7 +68,7 @@ def test_open_channel_against_oracle(collision):
     assert int(ens.flags().sum()) == 0
     ens.close()
     for i, m in enumerate(MEMBERS):
-        ch, fout, ref = _oracle(m, OPEN, 31, i, 1e-3, steps, collision)
+        ch, fout, ref = _oracle(m, op, 31, i, 1e-3, steps, collision)
         fluid = ~olbm.solid_mask(ch)
         e_drag = _rel(drag[i], ref)
         e_late = _rel(drag[i][200:], ref[200:])  # after the start-up pressure wave (drag ~50x larger)
