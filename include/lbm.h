@@ -230,9 +230,9 @@ int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third
  * columns from the inlet (sq_x0 >= 2) and three from the outlet
  * (sq_x0 + s <= nx - 3); 0 <= u_c <= 0.3; sponge_tau > 1/2; ny <= 2048
  * (LBM_EUNSUPPORTED beyond: the ghost kernel keeps a column in LDS).  The body
- * force of the members still applies.  Open channels step one lattice step
- * per launch (the ghost column is rebuilt between steps) plus one small
- * launch per step for the ghost columns.  lbm_init then starts every member
+ * force of the members still applies.  A small kernel rebuilds the ghost
+ * columns before every launch; the two-step shapes build the outlet column
+ * of their second step themselves.  lbm_init then starts every member
  * from the inlet profile (lbm_init_flow requires ux0 = 0).  oc = NULL
  * restores periodic channels.  Call before lbm_init; synchronises the
  * context's stream; allocates 9 * sum(ny) floats of library scratch for the

@@ -156,16 +156,15 @@ static bool two_step_now(const lbm_ctx* c) {
 
 // Tables of the current tile shape.  A two-step shape applies when every
 // member's width is a multiple of 256 and its block fits 32-bit byte
-// offsets, and the channels are periodic; otherwise (and for the last step
-// of an odd chunk) the library steps with the one-step shape 0, which gives
-// the same results.
+// offsets; otherwise (and for the last step of an odd chunk) the library
+// steps with the one-step shape 0, which gives the same results.
 static int build_segments(lbm_ctx* c) {
     const TileShape ts = TILE_SHAPES[c->tile_id];
     c->two_step = false;
     c->one_tile = c->tile_id;
     if (ts.steps == 2) {
         c->one_tile = 0;
-        bool ok = !c->open;  // the outlet ghost column is rebuilt between steps
+        bool ok = true;
         for (int m = 0; m < c->n; ++m)
             ok = ok && c->desc[m].nx % 256 == 0 && 36LL * c->desc[m].nx * c->desc[m].ny < (1LL << 31);
         if (ok) {
@@ -415,7 +414,7 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
     a.active_list = nullptr;
     a2.active_list = nullptr;
     a.ghost = c->open ? c->d_ghost : nullptr;
-    a2.ghost = nullptr;
+    a2.ghost = a.ghost;
     GhostArgs g;
     g.members = c->d_members;
     g.parity = c->d_parity;
@@ -444,6 +443,10 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
             for (; s + 1 < chunk; s += 2, ++launches) {
                 a2.slot = s;
                 a2.flip = launches & 1;
+                if (c->open) {  // the inlet's values and the outlet ghost column of the first of the two steps
+                    g.flip = a2.flip;
+                    if ((e = launch_outlet_ghost(g, c->n, c->max_ny, st)) != hipSuccess) return e;
+                }
                 if ((e = launch_step2(waves2, a2, c->model, st)) != hipSuccess) return e;
             }
         for (; s < chunk; ++s, ++launches) {

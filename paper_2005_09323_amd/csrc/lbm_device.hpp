@@ -229,6 +229,57 @@ __device__ __forceinline__ float inlet_dev(const MemberDev& m, int i, int y) {
     return (float)(WD[i] * (3.0 * u + 3.0 * (u * u)));
 }
 
+// Open channel outlet (paper Section 2): the velocity sum c_i f_i / sum f_i of
+// one stored (post-collision) cell from its FP32 deviations.
+__device__ __forceinline__ void stored_velocity(const float dl[9], double& ux, double& uy) {
+    double d[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = (double)dl[i];
+    const double rho = 1.0 + (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8]);
+    const double inv = 1.0 / rho;
+    ux = (((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7])) * inv;
+    uy = (((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8])) * inv;
+}
+
+// The velocities of the last two columns of one row: (ux1, uy1) at nx - 1,
+// (ux2, uy2) at nx - 2.
+struct OutletVel {
+    double ux1, uy1, ux2, uy2;
+};
+
+// Outlet ghost population of a direction with c_x = -1 at row y, as a
+// deviation from its weight w:
+//   rho_g = 1,  u_g = 2 u(nx-1) - u(nx-2),
+//   S_xx = ux(nx-1) - ux(nx-2),  S_yy = d_y uy_g,
+//   S_xy = (d_y ux_g + uy(nx-1) - uy(nx-2)) / 2
+//   (d_y centred over rows ya = y - 1 and yb = y + 1, one-sided in the first
+//   and last row, where the caller passes ya = y or yb = y),
+//   Pi = -2 c_s^2 (tau(nx-1) - 1) S,
+//   g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) : Pi.
+// The ghost kernel and the two-step kernel both build the ghost column with
+// this function; contraction into FMAs is off so that both give the same bits
+// wherever they are inlined.
+// (cx, cy, w: the direction's velocity and weight, passed as values so that
+// lanes can build different directions at once.)
+__device__ __forceinline__ float outlet_ghost_value(const MemberDev& m, double cx, double cy, double w, int y,
+                                                    const OutletVel& va, const OutletVel& v0, const OutletVel& vb) {
+#pragma clang fp contract(off)
+    const double h = (y > 0 && y + 1 < m.ny) ? 0.5 : 1.0;  // centred or one-sided
+    const double ux = 2.0 * v0.ux1 - v0.ux2, uy = 2.0 * v0.uy1 - v0.uy2;
+    const double uxa = 2.0 * va.ux1 - va.ux2, uya = 2.0 * va.uy1 - va.uy2;
+    const double uxb = 2.0 * vb.ux1 - vb.ux2, uyb = 2.0 * vb.uy1 - vb.uy2;
+    const double sxx = v0.ux1 - v0.ux2;
+    const double syy = h * (uyb - uya);
+    const double sxy = 0.5 * (h * (uxb - uxa) + (v0.uy1 - v0.uy2));
+    const double tau_out = m.sp_x0 < m.nx - 1 ? m.tau + (m.tau_sp - m.tau) : m.tau;  // tau(nx - 1), r = 1
+    const double cpi = -2.0 * (1.0 / 3.0) * (tau_out - 1.0);                        // Pi = cpi * S (rho_g = 1)
+    const double pxx = cpi * sxx, pyy = cpi * syy, pxy = cpi * sxy;
+    const double usq = ux * ux + uy * uy;
+    const double cu = cx * ux + cy * uy;
+    const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
+    return (float)(w * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+}
+
 // Directions of (x, y) whose next cell lies in the square (x-moving ones only).
 __device__ __forceinline__ unsigned square_links(const MemberDev& m, int x, int y) {
     unsigned mask = 0;

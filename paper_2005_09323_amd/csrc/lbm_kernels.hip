@@ -244,17 +244,9 @@ __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1
 // the member's [9][ny] ghost block: the +x movers (i = 1, 5, 8) of the inlet
 // column x = -1, which the cells of column 0 pull, and the -x movers
 // (i = 3, 6, 7) of the outlet column x = nx, which the cells of column nx - 1
-// pull.  The inlet is the equilibrium of the parabolic profile (inlet_dev).
-// The outlet comes from the post-collision state about to be streamed.  Per row y, with
-// (rho_k, u_k) the density and velocity sum c_i f_i / rho of the stored
-// populations of column k:
-//   rho_g = 1,  u_g = 2 u_{nx-1} - u_{nx-2},
-//   S_xx = ux_{nx-1} - ux_{nx-2},  S_yy = d_y uy_g,
-//   S_xy = (d_y ux_g + uy_{nx-1} - uy_{nx-2}) / 2
-//   (d_y: centred differences over rows, one-sided in the first and last row),
-//   Pi = -2 c_s^2 (tau_out - 1) S with tau_out the outlet column's relaxation time,
-//   g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) : Pi,
-// stored as deviations g_i - w_i in the member's [9][ny] block.
+// pull.  The inlet is the equilibrium of the parabolic profile (inlet_dev);
+// the outlet is outlet_ghost_value of the post-collision state about to be
+// streamed.
 // One workgroup per member: each thread takes rows t, t + 256, ... and puts
 // the velocities of the last two columns into LDS ([4][ny] doubles); after a
 // barrier every thread rebuilds the ghost populations of its rows from its
@@ -263,7 +255,7 @@ __global__ __launch_bounds__(256) void outlet_ghost_kernel(GhostArgs a) {
     const int mi = (int)blockIdx.x;
     const MemberDev m = a.members[mi];
     if (!m.open || !a.active[mi]) return;  // the whole workgroup
-    extern __shared__ double vel[];        // ux1[ny], uy1[ny], ux2[ny], uy2[ny]
+    extern __shared__ OutletVel vel[];      // [ny]
     const int par = a.parity[mi] ^ a.flip;
     const float* __restrict__ src = (par ? a.pop1 : a.pop0) + m.off;
     const int nx = m.nx, ny = m.ny;
@@ -276,45 +268,19 @@ __global__ __launch_bounds__(256) void outlet_ghost_kernel(GhostArgs a) {
             d1[i] = src[row + (unsigned)(nx - 1)];
             d2[i] = src[row + (unsigned)(nx - 2)];
         }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            double d[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] = (double)(c == 0 ? d1[i] : d2[i]);
-            const double rho = 1.0 + (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8]);
-            vel[(2 * c) * ny + y] = (((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7])) / rho;
-            vel[(2 * c + 1) * ny + y] = (((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8])) / rho;
-        }
+        OutletVel v;
+        stored_velocity(d1, v.ux1, v.uy1);
+        stored_velocity(d2, v.ux2, v.uy2);
+        vel[y] = v;
     }
     __syncthreads();
-    const double* ux1 = vel;
-    const double* uy1 = vel + ny;
-    const double* ux2 = vel + 2 * ny;
-    const double* uy2 = vel + 3 * ny;
-    const double tau_out = m.sp_x0 < nx - 1 ? m.tau + (m.tau_sp - m.tau) : m.tau;  // tau(nx - 1), r = 1
-    const double cpi = -2.0 * (1.0 / 3.0) * (tau_out - 1.0);                      // Pi = cpi * S (rho_g = 1)
     float* __restrict__ g = a.ghost + m.ghost_off;
     for (int y = (int)threadIdx.x; y < ny; y += 256) {
-        const int ya = y > 0 ? y - 1 : 0, yb = y + 1 < ny ? y + 1 : ny - 1;
-        const double h = (y > 0 && y + 1 < ny) ? 0.5 : 1.0;  // centred or one-sided
-        const double ux = 2.0 * ux1[y] - ux2[y], uy = 2.0 * uy1[y] - uy2[y];
-        const double uxa = 2.0 * ux1[ya] - ux2[ya], uya = 2.0 * uy1[ya] - uy2[ya];
-        const double uxb = 2.0 * ux1[yb] - ux2[yb], uyb = 2.0 * uy1[yb] - uy2[yb];
-        const double sxx = ux1[y] - ux2[y];
-        const double syy = h * (uyb - uya);
-        const double sxy = 0.5 * (h * (uxb - uxa) + (uy1[y] - uy2[y]));
-        const double pxx = cpi * sxx, pyy = cpi * syy, pxy = cpi * sxy;
-        const double usq = ux * ux + uy * uy;
+        const OutletVel va = vel[y > 0 ? y - 1 : 0], v0 = vel[y], vb = vel[y + 1 < ny ? y + 1 : ny - 1];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            if (CX[i] == 1) {
-                g[i * ny + y] = inlet_dev(m, i, y);
-            } else if (CX[i] == -1) {
-                const double cx = CX[i], cy = CY[i];
-                const double cu = cx * ux + cy * uy;
-                const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
-                g[i * ny + y] = (float)(WD[i] * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
-            }
+            if (CX[i] == 1) g[i * ny + y] = inlet_dev(m, i, y);
+            else if (CX[i] == -1) g[i * ny + y] = outlet_ghost_value(m, CX[i], CY[i], WD[i], y, va, v0, vb);
         }
     }
 }

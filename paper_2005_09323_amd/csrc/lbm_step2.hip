@@ -18,6 +18,16 @@
 // bit-identical states and drag.  The next iteration's row loads are issued
 // before the current row is collided and stay in flight across the
 // workgroup barriers, which wait for LDS traffic only.
+//
+// Open channels (OPEN): the strip at x = 0 takes the inlet's values from the
+// ghost block for both steps (they are constant); the strip at the outlet
+// takes the ghost column of step t+1 from the ghost block (built from the
+// state at t by the ghost kernel) and builds that of step t+2 itself: phase A
+// keeps the velocities of the last two columns of every row in a small LDS
+// ring, and phase B trails phase A by two rows, so that the rows a ghost
+// value needs (its own and the two neighbours of each of the three rows a
+// cell pulls from) are collided before it is used.  Grid bars are solid like
+// the square; sponge rates are set per cell.
 #include "lbm_device.hpp"
 
 namespace lbm {
@@ -45,8 +55,12 @@ __device__ __forceinline__ void lds_barrier() {
 // through L2 (not non-temporal): the neighbouring strip, on the same XCD and
 // near the same row, reads the words just outside this strip, and finds them
 // there (measured: 7 % instead of 12 % extra HBM fetch, 1.6 % faster).
+// OPEN: at the channel's ends the edge words come from the ghost block
+// (ghost != nullptr for the strips at x = 0 (left_end) and x = nx (right_end)).
+template <bool OPEN>
 __device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsrc_t rs, unsigned voff, int xl, int xr,
-                                         int y, RowLoads& L) {
+                                         int y, RowLoads& L, const float* __restrict__ ghost, bool left_end,
+                                         bool right_end) {
     const unsigned plane = (unsigned)m.nx * (unsigned)m.ny;
     const unsigned rowoff = (unsigned)y * (unsigned)m.nx;
 #pragma unroll
@@ -55,33 +69,56 @@ __device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsr
         const bool wall = ys < 0 || ys >= m.ny;
         const unsigned row = wall ? (unsigned)OPP[i] * plane + rowoff : (unsigned)i * plane + (unsigned)ys * (unsigned)m.nx;
         L.v[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * row, 0);
-        L.e[i] = CX[i] == 1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0))
-                            : (CX[i] == -1 ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0))
-                                           : 0.0f);
+        const unsigned gi = (unsigned)i * (unsigned)m.ny + (unsigned)(wall ? y : ys);
+        if (CX[i] == 1)
+            L.e[i] = (OPEN && left_end) ? ghost[gi]
+                                        : __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0));
+        else if (CX[i] == -1)
+            L.e[i] = (OPEN && right_end) ? ghost[gi]
+                                         : __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0));
+        else
+            L.e[i] = 0.0f;
     }
 }
 
 // Collide the lane's four cells of row y in place; ring cells leave their
-// drag partial in part.
-template <int MODEL>
+// drag partial in part.  sponge: the strip reaches an open channel's sponge
+// zone (rates per cell).
+template <int MODEL, bool OPEN>
 __device__ __forceinline__ void collide_row(const MemberDev& m, f4 p[9], double* __restrict__ part, bool near_sq, int x0,
-                                            int y) {
+                                            int y, bool sponge) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         float dl[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) dl[i] = p[i][k];
         const int ri = (near_sq && !in_square(m, x0 + k, y)) ? ring_index(m, x0 + k, y) : -1;
-        const double drag = collide_cell<MODEL>(m, dl, ri >= 0 ? square_links(m, x0 + k, y) : 0u);
+        const unsigned links = ri >= 0 ? square_links(m, x0 + k, y) : 0u;
+        double drag;
+        if (OPEN) {
+            MemberDev mc = m;
+            if (sponge) sponge_at(mc, x0 + k);
+            drag = collide_cell<MODEL>(mc, dl, links);
+        } else {
+            drag = collide_cell<MODEL>(m, dl, links);
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) p[i][k] = dl[i];
         if (ri >= 0) part[ri] = drag;
     }
 }
 
-template <int NW, int MODEL>
+// Velocity ring of the outlet strip: rows y & (VROWS - 1).  Phase B reads
+// rows r - 2 .. r + 2 while phase A writes up to r + 2 + NW - 1, so 16 rows
+// hold every row still needed for NW <= 8.
+constexpr int VROWS = 16;
+
+template <int NW, int MODEL, bool OPEN>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void step2_kernel(StepArgs a) {
-    __shared__ f4 ring4[(NW + 2) * 9 * RING_ROW / 4];
+    constexpr int LAG = OPEN ? 2 : 1;          // phase B works on row y - LAG
+    constexpr int RROWS = NW + 1 + LAG;        // ring rows: y - LAG - 1 .. y for the whole workgroup
+    __shared__ f4 ring4[RROWS * 9 * RING_ROW / 4];
+    __shared__ OutletVel vring[OPEN ? VROWS : 1];
     float* const ring = (float*)ring4;
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec;
@@ -94,6 +131,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     float* __restrict__ dst = (par ? a.pop0 : a.pop1) + m.off;
     double* __restrict__ part0 = a.partial + m.part_off + (long long)a.slot * m.ring;  // step t+1
     double* __restrict__ part1 = part0 + m.ring;                                         // step t+2
+    const float* __restrict__ ghost = OPEN ? a.ghost + m.ghost_off : nullptr;
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nx = m.nx, ny = m.ny;
@@ -104,13 +142,47 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int base = tx * 256;
     const int x0 = base + 4 * lane;
     const unsigned voff = 4u * (unsigned)x0;
-    const int xl = (base == 0 ? nx : base) - 1;      // the cell left of the strip (periodic)
-    const int xr = (base + 256 == nx) ? 0 : base + 256;  // the cell right of it
+    const bool left_end = base == 0, right_end = base + 256 == nx;
+    const int xl = (left_end ? nx : base) - 1;      // the cell left of the strip (periodic)
+    const int xr = right_end ? 0 : base + 256;      // the cell right of it
     const int xh = (lane & 1) ? xr : xl;             // lanes 0 / 1 collide the left / right outside cell
+    // OPEN: an end of the channel has no outside cell to collide (the inlet's
+    // values come from the ghost block, the outlet's are built in phase B)
+    const bool own_h = !OPEN || !((lane & 1) ? right_end : left_end);
     const bool sq_cols = m.ss > 0 && base <= m.sx0 + m.ss && base + 255 >= m.sx0 - 1;
-    const int iters = ny / NW + 1;                   // phase B of the last iteration reaches row ny - 1
+    const bool grid_cols = OPEN && m.bar > 0 && base <= m.gx0 + m.bar && base + 255 >= m.gx0 - 1;
+    const bool sponge = OPEN && base + 255 > m.sp_x0;
+    // bit j: column x0 - 1 + j (j = 0..5) holds grid bars
+    unsigned gcols = 0;
+    if (grid_cols)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) gcols |= ((unsigned)(x0 - 1 + j - m.gx0) < (unsigned)m.bar ? 1u : 0u) << j;
+    // OPEN: which rows cross the grid's bars, one bit per row (ny <= 2048),
+    // filled once per workgroup so that no row test needs an integer division
+    __shared__ unsigned gbits[OPEN ? 64 : 1];
+    if (OPEN && grid_cols) {
+        for (int w = (int)threadIdx.x; w < (ny + 31) / 32; w += 64 * NW) {
+            unsigned bits = 0;
+            for (int k = 0; k < 32 && 32 * w + k < ny; ++k) bits |= (grid_row(m, 32 * w + k) ? 1u : 0u) << k;
+            gbits[w] = bits;
+        }
+        lds_barrier();
+    }
+    auto grow = [&](int yy) {  // row yy crosses the grid's bars (false outside the lattice)
+        return OPEN && grid_cols && yy >= 0 && yy < ny && ((gbits[yy >> 5] >> (yy & 31)) & 1u);
+    };
+    // bits 0, 1, 2: rows yy - 1, yy, yy + 1 cross the grid's bars (read once per row and phase)
+    auto rows3 = [&](int yy) -> unsigned {
+        return OPEN ? (grow(yy - 1) ? 1u : 0u) | (grow(yy) ? 2u : 0u) | (grow(yy + 1) ? 4u : 0u) : 0u;
+    };
+    // solid test of column x0 + dx (dx = -1 .. 4) in row yy = row - 1 + j (0 <= yy < ny) of a
+    // row whose grid rows are g3; near: the row is near the square
+    auto solid = [&](int dx, int yy, int j, bool near, unsigned g3) {
+        return (near && in_square(m, x0 + dx, yy)) || (OPEN && ((gcols >> (dx + 1)) & (g3 >> j) & 1u));
+    };
+    const int iters = (ny + LAG - 1) / NW + 1;      // phase B of the last iteration reaches row ny - 1
     RowLoads cur;
-    if (wv < ny) load_row(m, rs, voff, xl, xr, wv, cur);
+    if (wv < ny) load_row<OPEN>(m, rs, voff, xl, xr, wv, cur, ghost, left_end, right_end);
 #pragma unroll 1
     for (int j = 0; j < iters; ++j) {
         const int y = j * NW + wv;
@@ -121,10 +193,25 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         // flight.
         const bool row_a = y < ny;
         const bool near_sq = row_a && sq_cols && y >= m.sy0 - 1 && y <= m.sy0 + m.ss;
+        const unsigned gA = row_a ? rows3(y) : 0u;
+        const bool near_a = near_sq || gA != 0u;
         float hv[9];
         f4 p[9];
         if (row_a) {
-            load_cell<false>(m, src, xh, y, hv);
+            if (own_h) {
+                if (OPEN) {  // an interior outside cell: no wrap; the grid's rows from the bit table
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const int xs = xh - CX[i], ys = y - CY[i];
+                        const bool bounce = ys < 0 || ys >= ny || in_square(m, xs, ys) ||
+                                            ((unsigned)(xs - m.gx0) < (unsigned)m.bar && ((gA >> (1 - CY[i])) & 1u));
+                        hv[i] = src[bounce ? (unsigned)OPP[i] * plane + (unsigned)y * (unsigned)nx + (unsigned)xh
+                                           : (unsigned)i * plane + (unsigned)ys * (unsigned)nx + (unsigned)xs];
+                    }
+                } else {
+                    load_cell<false>(m, src, xh, y, hv);
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int ys = y - CY[i];
@@ -142,39 +229,71 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     p[i] = v;
                 }
             }
-            if (near_sq) {
+            if (near_a) {
                 const unsigned rowoff = (unsigned)y * (unsigned)nx;
 #pragma unroll
-                for (int i = 1; i < 9; ++i) {
-                    const int ys = y - CY[i];
-                    if (ys < 0 || ys >= ny) continue;
+                for (int k = 0; k < 4; ++k) {
+                    if (solid(k, y, 1, near_sq, gA)) continue;  // a solid cell's results are never stored
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (in_square(m, x0 + k - CX[i], ys)) p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+                    for (int i = 1; i < 9; ++i) {
+                        const int ys = y - CY[i];
+                        if (ys < 0 || ys >= ny) continue;
+                        if (solid(k - CX[i], ys, 1 - CY[i], near_sq, gA))
+                            p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+                    }
                 }
             }
         }
         RowLoads nxt;
-        if (y + NW < ny) load_row(m, rs, voff, xl, xr, y + NW, nxt);
+        if (y + NW < ny) load_row<OPEN>(m, rs, voff, xl, xr, y + NW, nxt, ghost, left_end, right_end);
         if (row_a) {
-            float* row = ring + (y % (NW + 2)) * 9 * RING_ROW;
-            collide_row<MODEL>(m, p, part0, near_sq, x0, y);
+            float* row = ring + (y % RROWS) * 9 * RING_ROW;
+            collide_row<MODEL, OPEN>(m, p, part0, near_sq, x0, y, sponge);
 #pragma unroll
             for (int i = 0; i < 9; ++i) *(f4*)(row + i * RING_ROW + RING_CELL0 + 4 * lane) = p[i];
-            // the outside cells (their drag belongs to the neighbouring strip)
-            collide_cell<MODEL>(m, hv, 0u);
-            if (lane < 2 && !in_square(m, xh, y)) {
-                const int at = lane ? RING_RIGHT : RING_LEFT;
+            if (OPEN && right_end && lane == 63) {  // the velocities the outlet ghost of step t+2 needs
+                float d1[9], d2[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) row[i * RING_ROW + at] = hv[i];
+                for (int i = 0; i < 9; ++i) {
+                    d1[i] = p[i][3];  // column nx - 1
+                    d2[i] = p[i][2];  // column nx - 2
+                }
+                OutletVel v;
+                stored_velocity(d1, v.ux1, v.uy1);
+                stored_velocity(d2, v.ux2, v.uy2);
+                vring[y & (VROWS - 1)] = v;
+            }
+            // the outside cells (their drag belongs to the neighbouring strip)
+            if (own_h) {
+                if (OPEN) {
+                    MemberDev mc = m;
+                    if (sponge || base + 256 > m.sp_x0) sponge_at(mc, xh);
+                    collide_cell<MODEL>(mc, hv, 0u);
+                } else {
+                    collide_cell<MODEL>(m, hv, 0u);
+                }
+            }
+            if (lane < 2) {
+                const int at = lane ? RING_RIGHT : RING_LEFT;
+                if (own_h) {
+                    if (!(in_square(m, xh, y) || (OPEN && (unsigned)(xh - m.gx0) < (unsigned)m.bar && ((gA >> 1) & 1u))))
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) row[i * RING_ROW + at] = hv[i];
+                } else if (lane == 0) {  // the inlet's +x movers for both steps
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        if (CX[i] == 1) row[i * RING_ROW + at] = ghost[(unsigned)i * (unsigned)ny + (unsigned)y];
+                }
             }
         }
         lds_barrier();
-        // phase B: row y - 1 at step t+2 from the ring to the other buffer
-        const int r = y - 1;
+        // phase B: row y - LAG at step t+2 from the ring to the other buffer
+        const int r = y - LAG;
         if (r >= 0 && r < ny) {
-            const float* own = ring + (r % (NW + 2)) * 9 * RING_ROW;
+            const float* own = ring + (r % RROWS) * 9 * RING_ROW;
             const bool near_sq = sq_cols && r >= m.sy0 - 1 && r <= m.sy0 + m.ss;
+            const unsigned gB = rows3(r);
+            const bool near_b = near_sq || gB != 0u;
             f4 p[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -183,40 +302,55 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     p[i] = *(const f4*)(own + OPP[i] * RING_ROW + RING_CELL0 + 4 * lane);
                     continue;
                 }
-                const float* srow = ring + (rsrc % (NW + 2)) * 9 * RING_ROW + i * RING_ROW;
+                const float* srow = ring + (rsrc % RROWS) * 9 * RING_ROW + i * RING_ROW;
                 const f4 v = *(const f4*)(srow + RING_CELL0 + 4 * lane);
                 if (CX[i] == 1) {
                     const float h = srow[RING_LEFT];
                     const float sh = wave_shr1(v.w);
                     p[i] = f4{lane == 0 ? h : sh, v.x, v.y, v.z};
                 } else if (CX[i] == -1) {
-                    const float h = srow[RING_RIGHT];
+                    float h;
+                    if (OPEN && right_end) {  // the outlet ghost column of step t+1, row rsrc
+                        const OutletVel va = vring[(rsrc > 0 ? rsrc - 1 : 0) & (VROWS - 1)];
+                        const OutletVel v0 = vring[rsrc & (VROWS - 1)];
+                        const OutletVel vb = vring[(rsrc + 1 < ny ? rsrc + 1 : ny - 1) & (VROWS - 1)];
+                        h = outlet_ghost_value(m, CX[i], CY[i], WD[i], rsrc, va, v0, vb);
+                    } else {
+                        h = srow[RING_RIGHT];
+                    }
                     const float sh = wave_shl1(v.x);
                     p[i] = f4{v.y, v.z, v.w, lane == 63 ? h : sh};
                 } else {
                     p[i] = v;
                 }
             }
-            if (near_sq) {
+            if (near_b) {
 #pragma unroll
-                for (int i = 1; i < 9; ++i) {
-                    const int rsrc = r - CY[i];
-                    if (rsrc < 0 || rsrc >= ny) continue;
+                for (int k = 0; k < 4; ++k) {
+                    if (solid(k, r, 1, near_sq, gB)) continue;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (in_square(m, x0 + k - CX[i], rsrc)) p[i][k] = own[OPP[i] * RING_ROW + RING_CELL0 + 4 * lane + k];
+                    for (int i = 1; i < 9; ++i) {
+                        const int rsrc = r - CY[i];
+                        if (rsrc < 0 || rsrc >= ny) continue;
+                        if (solid(k - CX[i], rsrc, 1 - CY[i], near_sq, gB))
+                            p[i][k] = own[OPP[i] * RING_ROW + RING_CELL0 + 4 * lane + k];
+                    }
                 }
             }
-            collide_row<MODEL>(m, p, part1, near_sq, x0, r);
+            collide_row<MODEL, OPEN>(m, p, part1, near_sq, x0, r, sponge);
             const unsigned rowoff = (unsigned)r * (unsigned)nx;
-            if (!near_sq) {
+            unsigned smask = 0;  // bit k: cell x0 + k is solid
+            if (near_b)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) smask |= (solid(k, r, 1, near_sq, gB) ? 1u : 0u) << k;
+            if (smask == 0) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
                     __builtin_amdgcn_raw_buffer_store_b128(p[i], rd, voff, 4u * ((unsigned)i * plane + rowoff), BUFFER_NT);
-            } else {
+            } else if (smask != 0xFu) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (in_square(m, x0 + k, r)) continue;
+                    if ((smask >> k) & 1u) continue;
 #pragma unroll
                     for (int i = 0; i < 9; ++i) dst[(unsigned)i * plane + rowoff + (unsigned)(x0 + k)] = p[i][k];
                 }
@@ -229,10 +363,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 
 template <int NW>
 static hipError_t launch_step2_t(const StepArgs& a, int model, hipStream_t st) {
-    if (model == 1)
-        hipLaunchKernelGGL((step2_kernel<NW, 1>), dim3(a.total_blocks), dim3(64 * NW), 0, st, a);
-    else
-        hipLaunchKernelGGL((step2_kernel<NW, 0>), dim3(a.total_blocks), dim3(64 * NW), 0, st, a);
+    const dim3 grid(a.total_blocks), block(64 * NW);
+    if (a.ghost) {
+        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((step2_kernel<NW, 0, true>), grid, block, 0, st, a);
+    } else {
+        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((step2_kernel<NW, 0, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 

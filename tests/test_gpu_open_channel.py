@@ -257,3 +257,45 @@ def test_gktl_run_on_open_channel_matches_oracle():
     ref_fmax = ogktl.window_mean_max(ref_series, window)
     assert np.allclose(fmax.cpu().numpy(), ref_fmax, rtol=1e-5)
     ens.close()
+
+
+@pytest.mark.parametrize("collision", [None, CM_RATES])
+def test_open_channel_two_step_bit_identical_to_one_step(collision):
+    """Widths that are multiples of 256: the two-step kernel (inlet values from the ghost block,
+    the outlet ghost column of its second step built in the kernel) against the one-step shape 0,
+    bit for bit; a single-strip lattice (inlet and outlet in one strip), an odd step count, an
+    inactive member; the oracle on the result."""
+    members = [workloads.Member(512, 40, 0.56, 0.0, (200, 15, 8)),
+               workloads.Member(512, 40, 0.6, 1e-6, (300, 10, 6)),
+               workloads.Member(512, 40, 0.56, 0.0, (200, 15, 8))]
+    op = workloads.OpenParams(0.05, 20, 6, 400, 0.9)
+    single = [workloads.Member(256, 33, 0.58, 0.0, (100, 12, 8))]
+    op_single = workloads.OpenParams(0.04, 30, 4, 200, 0.8)
+    steps = 151
+    for mem, o in ((members, op), (single, op_single)):
+        runs = {}
+        for tile in (0, 16, 17, 18, 19, 20):
+            ens = _ensemble(mem, steps + 40, o, collision, tile=tile)
+            ens.init(41, 1e-3)
+            if tile in (16, 17, 18, 19):
+                assert ens.launch_steps() == 2
+            ens.step(steps - 1)
+            if len(mem) > 1:
+                ens.set_active([1, 0, 1])
+                ens.step(33)
+                ens.set_active(None)
+            torch.cuda.synchronize()
+            runs[tile] = ([ens.time(i) for i in range(len(mem))], ens.drag(0, steps + 33).cpu().numpy(),
+                          [ens.state(i).cpu().numpy().copy() for i in range(len(mem))])
+            ens.close()
+        t0, d0, s0 = runs[0]
+        for tile, (t, d, st) in runs.items():
+            assert t == t0, tile
+            for i, m in enumerate(mem):
+                fluid = ~olbm.solid_mask(_channel(m, o))
+                n_i = t0[i]
+                assert np.array_equal(d[i][:n_i], d0[i][:n_i]), (tile, i)
+                assert np.array_equal(st[i][:, fluid], s0[i][:, fluid]), (tile, i)
+        m = mem[-1]
+        _, _, ref = _oracle(m, o, 41, len(mem) - 1, 1e-3, steps, collision)
+        assert _rel(d0[len(mem) - 1][:steps], ref) <= 1e-5
