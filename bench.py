@@ -91,6 +91,20 @@ def copy_calibration(mib: int, reps: int) -> None:
           flush=True)
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Read + write GB/s of a plain device-to-device copy of `mib` MiB (the box's practical ceiling)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = _timed(lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 8 * n / (ms / 1e3) / 1e9
+
+
 def _timed(fn, reps=1):
     """Milliseconds per call of fn on the current stream (HIP events)."""
     import torch
@@ -321,6 +335,10 @@ def main():
     ens.close()
     del ens
     torch.cuda.empty_cache()
+    # the same launch priced against a plain copy on this machine (its practical HBM ceiling)
+    cbw = copy_bandwidth()
+    out["copy_reference"] = {"GBs": round(cbw, 1), "frac_of_copy": round(achieved / cbw, 4),
+                             "what": "torch copy_ of 1 GiB FP32, read + write bytes"}
     if not args.no_legs:
         out["legs"] = legs()
         out["legs"]["face_diagnostics"] = {"workload": wl.name, "ms_per_call": round(diag_ms, 4)}

@@ -180,8 +180,9 @@ int lbm_flags(const lbm_ctx* ctx, int32_t* out_dev);
  *          - (1 - 1/(2 tau)) sum_i c_ia c_ib (f_i - f_i^eq)
  *   q = 3  mean shear on top:    (1/s) sum u_x over the top cells / (1/2)
  *   q = 4  mean shear on bottom: (1/s) sum (-u_x) over the bottom cells / (1/2)
- * with u the Guo-shifted velocity; zeros for members without a square.
- * Enqueued on the context's stream.
+ * with u the Guo-shifted velocity and tau the member's (an open channel's
+ * sponge is taken not to reach the square); zeros for members without a
+ * square.  Enqueued on the context's stream.
  */
 int lbm_face_diagnostics(const lbm_ctx* ctx, double* out_dev);
 
