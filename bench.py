@@ -123,11 +123,19 @@ KERNEL_SOURCES = ("common.hpp", "kernels.hpp", "lbm_device.hpp", "lbm_kernels.hi
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of the lattice kernels' sources (the counters in the traffic record belong to one version)."""
+    """Hash of the lattice kernels' code (the counters in the traffic record belong to one version).
+
+    Line comments, trailing blanks and empty lines are left out, so that a change of wording
+    does not retire the record; any change of code does."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2005_09323_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2005_09323_amd", "csrc", name)).read()
+        for line in text.splitlines():
+            code = re.sub(r"//.*$", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -6,11 +6,13 @@
 //
 //   phase A  each wave pulls one row of the state at t from HBM and collides
 //            it (step t+1) exactly as the one-step kernel does, and keeps the
-//            result in an LDS ring of NW + 2 rows.  The two cells just outside
-//            the strip (x0 - 1 and x0 + 256, periodic) are collided too, so
-//            that phase B never needs a neighbouring strip;
-//   phase B  each wave pulls the row below its phase-A row from the ring,
-//            collides it (step t+2) and writes it to the other buffer.
+//            result in an LDS ring of NW + 2 rows (NW + 3 for open channels).
+//            The two cells just outside the strip (x0 - 1 and x0 + 256,
+//            periodic) are collided too, so that phase B never needs a
+//            neighbouring strip;
+//   phase B  each wave pulls the row below its phase-A row (two rows below
+//            for open channels) from the ring, collides it (step t+2) and
+//            writes it to the other buffer.
 //
 // Every population is read from HBM once and written once per two steps
 // (plus 2 x 9 words per row for the outside cells).  The arithmetic of every
