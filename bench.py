@@ -190,6 +190,21 @@ def legs():
                         "mfma_TFLOPs_train": round(256 * flop_train / (t_train / 1e3) / 1e12, 3),
                         "mfma_TFLOPs_forward": round(256 * flop_fwd / (t_fwd / 1e3) / 1e12, 3)}
     del net, xt, lt
+    # uneven sizes in one launch: 64 members each of 256x64, 512x128 and 1024x256
+    wl = workloads.mixed_sizes()
+    ens = Ensemble(wl.members, series_capacity=300)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(20)
+    torch.cuda.synchronize()
+    t_mixed = _timed(lambda: ens.step(256)) / 256
+    fluid = sum(m.fluid_cells for m in wl.members)
+    out["mixed_sizes"] = {"workload": wl.name, "steps_per_launch": ens.launch_steps(),
+                          "ms_per_step": round(t_mixed, 4), "MLUPS": round(wl.cells / t_mixed / 1e3, 1),
+                          "GBs_72B_per_update": round(BYTES_PER_LUP * fluid / t_mixed / 1e6, 1),
+                          "nonfinite_members": int(ens.flags().sum().item())}
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
     # launch-bound batches (an AMS branch re-simulates a handful of members): full 64-step chunks
     # replayed from a captured HIP graph against launching every kernel of every chunk
     m = workloads.ams_ensemble().members[0]
