@@ -257,7 +257,7 @@ def main():
     ap.add_argument("--workload", default="ensemble", choices=["ensemble", "mixed", "single", "open"])
     ap.add_argument("--tile", type=int, default=16,
                     help="lattice launch shape (-1: autotune; 16, two steps per launch, is the profiled default)")
-    ap.add_argument("--cpu-steps", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=800, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_ensemble1024_traffic.json"))
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
                     help="copy: time a plain device copy of --copy-mib MiB (counter calibration)")
