@@ -271,6 +271,13 @@ int lbm_launch_steps(const lbm_ctx* ctx, int32_t* steps);
 /* Time every tile shape on this ensemble (n_steps each, on the context's
    stream, synchronising it) and keep the fastest.  Writes the chosen id. */
 int lbm_autotune(lbm_ctx* ctx, int32_t n_steps, int32_t* best_tile);
+/* lbm_autotune with a persisted table: path is a text file of lines
+   "<key>\t<tile id>", the key naming the runs of lattice shapes, the
+   collision and whether the channels are open.  A line with this context's
+   key sets its shape without timing anything; otherwise the context is tuned
+   and a line appended (the file is created if missing).  LBM_EINVAL if the
+   line cannot be written (the tuned shape is set all the same). */
+int lbm_autotune_cached(lbm_ctx* ctx, int32_t n_steps, const char* path, int32_t* best_tile);
 
 /*
  * GKTL cloning at the end of a period (paper Appendix C.1, weight equation;

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -737,5 +739,46 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     c->tile_id = best;
     build_segments(c);
     *best_tile = best;
+    return LBM_OK;
+}
+
+// What a tuned launch shape depends on: the runs of lattice shapes, the
+// collision and whether the channels are open.
+static std::string tune_key(const lbm_ctx* c) {
+    std::ostringstream k;
+    k << "model=" << c->model << " open=" << (c->open ? 1 : 0) << " shapes=";
+    int run = 0;
+    for (int m = 0; m < c->n; ++m) {
+        ++run;
+        if (m + 1 == c->n || c->desc[m + 1].nx != c->desc[m].nx || c->desc[m + 1].ny != c->desc[m].ny) {
+            k << c->desc[m].nx << "x" << c->desc[m].ny << "*" << run << ";";
+            run = 0;
+        }
+    }
+    return k.str();
+}
+
+extern "C" int lbm_autotune_cached(lbm_ctx* c, int32_t n_steps, const char* path, int32_t* best_tile) {
+    if (!c || !path || !best_tile) return lbm_fail(LBM_EINVAL, "NULL argument");
+    const std::string key = tune_key(c);
+    {
+        std::ifstream in(path);
+        std::string line;
+        while (in && std::getline(in, line)) {
+            const size_t tab = line.rfind('\t');
+            if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+            const int tile = std::atoi(line.c_str() + tab + 1);
+            if (tile < 0 || tile >= N_TILE_SHAPES) continue;  // a table from another build: tune again
+            const int rc = lbm_set_tile(c, tile);
+            if (rc) return rc;
+            *best_tile = tile;
+            return LBM_OK;
+        }
+    }
+    const int rc = lbm_autotune(c, n_steps, best_tile);
+    if (rc) return rc;
+    std::ofstream out(path, std::ios::app);
+    out << key << '\t' << *best_tile << '\n';
+    if (!out) return lbm_fail(LBM_EINVAL, "cannot append the tuned shape to %s", path);
     return LBM_OK;
 }

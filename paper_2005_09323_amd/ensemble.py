@@ -123,9 +123,13 @@ class Ensemble:
         native.check(self.lib.lbm_launch_steps(self._ctx, ctypes.byref(n)))
         return n.value
 
-    def autotune(self, n_steps: int = 20) -> int:
+    def autotune(self, n_steps: int = 20, table: Optional[str] = None) -> int:
+        """Time every launch shape and keep the fastest; with `table`, reuse or extend a persisted table."""
         best = ctypes.c_int32()
-        native.check(self.lib.lbm_autotune(self._ctx, n_steps, ctypes.byref(best)))
+        if table is None:
+            native.check(self.lib.lbm_autotune(self._ctx, n_steps, ctypes.byref(best)))
+        else:
+            native.check(self.lib.lbm_autotune_cached(self._ctx, n_steps, table.encode(), ctypes.byref(best)))
         return best.value
 
     def set_time(self, t: int) -> None:

@@ -429,3 +429,26 @@ def test_init_with_uniform_velocity_matches_oracle():
         fout, ref = olbm.run(ch, f0, steps)
         assert _rel(gpu[i], ref) <= 1e-5
         assert _state_err(ens, i, m, fout) <= 1e-4
+
+
+def test_autotune_table_is_reused(tmp_path):
+    """A tuned shape goes into the table under the ensemble's key, a new context with that key
+    reads it back, and a different collision is a different key (tuned and appended)."""
+    from paper_2005_09323_amd.ensemble import Ensemble
+    members = [workloads.Member(512, 64, 0.6, 1e-5, (100, 20, 8))] * 8
+    table = str(tmp_path / "tiles.txt")
+    ens = Ensemble(members, series_capacity=10)
+    t1 = ens.autotune(4, table=table)
+    ens.close()
+    lines = open(table).read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith("\t%d" % t1) and "512x64*8" in lines[0]
+    ens = Ensemble(members, series_capacity=10)
+    assert ens.autotune(4, table=table) == t1
+    assert len(open(table).read().splitlines()) == 1
+    ens.set_collision("central", 1.0, 1.0, 1.0)
+    ens.autotune(4, table=table)
+    assert len(open(table).read().splitlines()) == 2
+    ens.init(1, 1e-3)  # tuned before init, as the call requires
+    ens.step(3)
+    assert int(ens.flags().sum()) == 0
+    ens.close()

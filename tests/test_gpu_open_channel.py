@@ -263,16 +263,18 @@ def test_gktl_run_on_open_channel_matches_oracle():
 def test_open_channel_two_step_bit_identical_to_one_step(collision):
     """Widths that are multiples of 256: the two-step kernel (inlet values from the ghost block,
     the outlet ghost column of its second step built in the kernel) against the one-step shape 0,
-    bit for bit; a single-strip lattice (inlet and outlet in one strip), an odd step count, an
-    inactive member; the oracle on the result."""
+    bit for bit; a single-strip lattice (inlet and outlet in one strip), grid bars across a strip
+    seam, an odd step count, an inactive member; the oracle on the result."""
     members = [workloads.Member(512, 40, 0.56, 0.0, (200, 15, 8)),
                workloads.Member(512, 40, 0.6, 1e-6, (300, 10, 6)),
                workloads.Member(512, 40, 0.56, 0.0, (200, 15, 8))]
     op = workloads.OpenParams(0.05, 20, 6, 400, 0.9)
     single = [workloads.Member(256, 33, 0.58, 0.0, (100, 12, 8))]
     op_single = workloads.OpenParams(0.04, 30, 4, 200, 0.8)
+    straddle = [workloads.Member(512, 40, 0.56, 0.0, (300, 15, 8))] * 2
+    op_straddle = workloads.OpenParams(0.05, 252, 8, 300, 0.9)  # grid bars across the strip seam at x = 256
     steps = 151
-    for mem, o in ((members, op), (single, op_single)):
+    for mem, o in ((members, op), (single, op_single), (straddle, op_straddle)):
         runs = {}
         for tile in (0, 16, 17, 18, 19, 20):
             ens = _ensemble(mem, steps + 40, o, collision, tile=tile)
@@ -280,7 +282,7 @@ def test_open_channel_two_step_bit_identical_to_one_step(collision):
             if tile in (16, 17, 18, 19):
                 assert ens.launch_steps() == 2
             ens.step(steps - 1)
-            if len(mem) > 1:
+            if len(mem) > 2:
                 ens.set_active([1, 0, 1])
                 ens.step(33)
                 ens.set_active(None)
