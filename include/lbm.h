@@ -435,7 +435,8 @@ int score_net_forward(const float* params_dev, const float* x_dev, int32_t batch
  * Gradient of the mean squared error (1/B) sum_b (y_b - label_b)^2 with
  * respect to every parameter (device float[score_net_params()]), and the loss
  * into loss_dev (device float, may be NULL).  Deterministic: per-image
- * contributions are added in image order.
+ * contributions are added in image order within chunks of 64 images and the
+ * chunk sums in chunk order; the loss by a fixed-order tree.
  */
 int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
                    float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes, void* hip_stream);

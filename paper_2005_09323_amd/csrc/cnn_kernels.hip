@@ -362,28 +362,51 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
     conv_wgrad<3, 4>(bufd, bufx, part + CNN_OFF_W1, wave, lane);
 }
 
-// Gradients summed over the batch in image order; the read-out's own
-// gradients (w4, b4) and the loss from the saved averages.
-__global__ __launch_bounds__(256) void cnn_reduce_kernel(CnnArgs a) {
+// Gradients summed over the batch in a fixed order, in two passes: pass 1
+// sums each chunk of RED_CHUNK images in image order (the read-out's own
+// gradients w4, b4 from the saved averages) into the chunk's first partial
+// row, pass 2 sums those rows in chunk order and, in its first workgroup,
+// the loss (a fixed-order tree).  Deterministic for a given batch size.
+constexpr int RED_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void cnn_reduce_chunks_kernel(CnnArgs a) {
     const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q >= CNN_N_PARAMS) return;
+    const int b0 = (int)blockIdx.y * RED_CHUNK, b1 = min(b0 + RED_CHUNK, a.batch);
     float tot = 0.0f;
     if (q >= CNN_OFF_W4) {
-        for (int b = 0; b < a.batch; ++b) {
+        for (int b = b0; b < b1; ++b) {
             const float gy = 2.0f * (a.y[b] - a.labels[b]) / (float)a.batch;
             tot += q == CNN_OFF_B4 ? gy : gy * a.gap[(long long)b * NC + (q - CNN_OFF_W4)];
         }
     } else {
-        for (int b = 0; b < a.batch; ++b) tot += a.partial[(long long)b * CNN_N_PARAMS + q];
+        for (int b = b0; b < b1; ++b) tot += a.partial[(long long)b * CNN_N_PARAMS + q];
     }
-    a.grads[q] = tot;
-    if (q == 0 && a.loss) {
+    a.partial[(long long)b0 * CNN_N_PARAMS + q] = tot;  // the chunk's first row, read only by this thread
+}
+
+__global__ __launch_bounds__(256) void cnn_reduce_final_kernel(CnnArgs a) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int chunks = (a.batch + RED_CHUNK - 1) / RED_CHUNK;
+    if (q < CNN_N_PARAMS) {
+        float tot = 0.0f;
+        for (int c = 0; c < chunks; ++c) tot += a.partial[(long long)c * RED_CHUNK * CNN_N_PARAMS + q];
+        a.grads[q] = tot;
+    }
+    if (blockIdx.x == 0 && a.loss) {  // the whole first workgroup
+        __shared__ double red[256];
         double l = 0.0;
-        for (int b = 0; b < a.batch; ++b) {
+        for (int b = (int)threadIdx.x; b < a.batch; b += 256) {
             const double r = (double)a.y[b] - (double)a.labels[b];
             l += r * r;
         }
-        *a.loss = (float)(l / a.batch);
+        red[threadIdx.x] = l;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *a.loss = (float)(red[0] / a.batch);
     }
 }
 
@@ -443,7 +466,10 @@ hipError_t launch_cnn_backward(const CnnArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(cnn_backward_kernel, dim3(a.batch), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cnn_reduce_kernel, dim3((CNN_N_PARAMS + 255) / 256), dim3(256), 0, st, a);
+    const unsigned cols = (CNN_N_PARAMS + 255) / 256, chunks = (unsigned)((a.batch + RED_CHUNK - 1) / RED_CHUNK);
+    hipLaunchKernelGGL(cnn_reduce_chunks_kernel, dim3(cols, chunks), dim3(256), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(cnn_reduce_final_kernel, dim3(cols), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_cnn_adam(const AdamArgs& a, hipStream_t st) {
