@@ -12,11 +12,13 @@ using namespace lbm;
 namespace {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct WsLayout {
-    size_t act, gap, y, partial, total;
+    size_t wt, act, gap, y, partial, total;
 };
 WsLayout layout(int batch) {
     WsLayout w;
     size_t off = 0;
+    w.wt = off;
+    off += align256((size_t)CNN_WT_ELEMS * sizeof(unsigned short));
     w.act = off;
     off += align256((size_t)batch * 3 * 256 * 32 * sizeof(unsigned short));
     w.gap = off;
@@ -83,8 +85,8 @@ extern "C" int score_net_forward(const float* params_dev, const float* x_dev, in
     a.y = y_dev;
     a.gap = nullptr;
     a.act = nullptr;
+    a.wt = (unsigned short*)((char*)workspace + w.wt);
     hipError_t e = launch_cnn_forward(a, (hipStream_t)hip_stream);
-    (void)w;
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "score forward");
 }
 
@@ -107,6 +109,7 @@ extern "C" int score_net_grad(const float* params_dev, const float* x_dev, const
     a.partial = (float*)(base + w.partial);
     a.grads = grads_dev;
     a.loss = loss_dev;
+    a.wt = (unsigned short*)(base + w.wt);
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = launch_cnn_forward(a, st);
     if (e != hipSuccess) return lbm_hip_fail(e, "score forward");

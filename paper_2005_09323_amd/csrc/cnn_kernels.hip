@@ -10,8 +10,9 @@
 // operands rounded to nearest-even from FP32, FP32 accumulation.  One
 // workgroup (4 waves) owns one image; activations live in LDS as padded
 // 18 x 18 x C tiles (channel fastest), weights as [K][32] with
-// K = (tap, input channel).  Weight gradients are written per image and summed
-// in image order afterwards, so every result is deterministic.
+// K = (tap, input channel), staged in BF16 once per call.  Weight gradients
+// are written per image and summed in a fixed order afterwards, so every
+// result is deterministic.
 #include "cnn_kernels.hpp"
 
 namespace lbm {
@@ -39,18 +40,33 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 // Lane layout of the 16x16x16 BF16 MFMA: lane l supplies A[l % 16][4 (l / 16) + j]
 // and B[4 (l / 16) + j][l % 16] (j = 0..3) and receives D[4 (l / 16) + j][l % 16].
 
-// Weights of one layer into LDS as wt[k][o], k = tap * cin + c, zero rows up to kp.
-__device__ void load_weights(const float* __restrict__ w, int cin, int kp, unsigned short* wt) {
-    const int k_real = 9 * cin;
-    for (int e = (int)threadIdx.x; e < kp * NC; e += (int)blockDim.x) {
-        const int k = e / NC, o = e - k * NC;
-        float v = 0.0f;
-        if (k < k_real) {
-            const int tap = k / cin, c = k - tap * cin;
-            v = w[(o * cin + c) * 9 + tap];
-        }
-        wt[e] = f2bf(v);
+// The three layers' tables wt[k][o] (k = tap * cin + c, zero rows up to kp)
+// in BF16, once per call: layer 1 at 0 (kp = 32), layer 2 at 32 * 32, layer 3
+// at (32 + 288) * 32.
+__global__ __launch_bounds__(256) void cnn_stage_weights_kernel(const float* __restrict__ params,
+                                                                unsigned short* __restrict__ wt) {
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= CNN_WT_ELEMS) return;
+    int layer, r;
+    if (e < 32 * NC) { layer = 0; r = e; }
+    else if (e < (32 + 288) * NC) { layer = 1; r = e - 32 * NC; }
+    else { layer = 2; r = e - (32 + 288) * NC; }
+    const int cin = layer == 0 ? 3 : NC;
+    const float* w = params + (layer == 0 ? CNN_OFF_W1 : (layer == 1 ? CNN_OFF_W2 : CNN_OFF_W3));
+    const int k = r / NC, o = r - k * NC;
+    float v = 0.0f;
+    if (k < 9 * cin) {
+        const int tap = k / cin, c = k - tap * cin;
+        v = w[(o * cin + c) * 9 + tap];
     }
+    wt[e] = f2bf(v);
+}
+
+// One staged table (kp rows) into LDS with 16-byte copies.
+__device__ void copy_weights(const unsigned short* __restrict__ src, int kp, unsigned short* wt) {
+    const uint4* s4 = (const uint4*)src;
+    uint4* d4 = (uint4*)wt;
+    for (int e = (int)threadIdx.x; e < kp * NC / 8; e += (int)blockDim.x) d4[e] = s4[e];
 }
 
 __device__ void zero_lds(unsigned short* p, int n) {
@@ -81,14 +97,21 @@ __device__ void conv_fwd(const unsigned short* in, const unsigned short* wt, f32
         for (int mt = 0; mt < 4; ++mt) {
             const int y = wave * 4 + mt;
             bf16x4 afr;
+            if constexpr (CIN % 16 == 0) {
+                // the 16 k of a step share one tap and the lane's 4 are consecutive
+                // channels: one 8-byte LDS read
+                const int tp = (ks * 16) / CIN, dy = tp / 3, dx = tp - 3 * (tp / 3);
+                afr = *(const bf16x4*)(in + ((y + dy) * PADW + (col + dx)) * CSTRIDE + ch[0]);
+            } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                short v = 0;
-                if (tap[j] >= 0) {
-                    const int dy = tap[j] / 3, dx = tap[j] - 3 * (tap[j] / 3);
-                    v = (short)in[((y + dy) * PADW + (col + dx)) * CSTRIDE + ch[j]];
+                for (int j = 0; j < 4; ++j) {
+                    short v = 0;
+                    if (tap[j] >= 0) {
+                        const int dy = tap[j] / 3, dx = tap[j] - 3 * (tap[j] / 3);
+                        v = (short)in[((y + dy) * PADW + (col + dx)) * CSTRIDE + ch[j]];
+                    }
+                    afr[j] = v;
                 }
-                afr[j] = v;
             }
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(afr, bfr[nt], acc[mt][nt]);
@@ -101,26 +124,16 @@ __device__ void conv_fwd(const unsigned short* in, const unsigned short* wt, f32
 __device__ void conv_dgrad(const unsigned short* dz, const unsigned short* wt, f32x4 acc[4][2], int wave, int lane) {
     const int col = lane & 15, kq = (lane >> 4) * 4;
     for (int ks = 0; ks < 9 * NC / 16; ++ks) {
+        const int tap0 = (ks * 16) / NC;  // all 16 k of a step share one tap
+        const int o0 = ks * 16 + kq - tap0 * NC;  // the lane's 4 consecutive output channels
         bf16x4 bfr[2];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = ks * 16 + kq + j;
-                const int tap = k / NC, o = k - tap * NC;
-                bfr[nt][j] = (short)wt[(tap * NC + nt * 16 + col) * NC + o];
-            }
-        const int tap0 = (ks * 16) / NC;  // all 16 k of a step share one tap
+        for (int nt = 0; nt < 2; ++nt) bfr[nt] = *(const bf16x4*)(wt + (tap0 * NC + nt * 16 + col) * NC + o0);
         const int dy = tap0 / 3, dx = tap0 - 3 * (tap0 / 3);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int y = wave * 4 + mt;
-            bf16x4 afr;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = (ks * 16 + kq + j) - tap0 * NC;
-                afr[j] = (short)dz[((y - dy + 2) * PADW + (col - dx + 2)) * NC + o];
-            }
+            const bf16x4 afr = *(const bf16x4*)(dz + ((y - dy + 2) * PADW + (col - dx + 2)) * NC + o0);
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(afr, bfr[nt], acc[mt][nt]);
         }
@@ -230,9 +243,12 @@ __device__ void zero_acc(f32x4 acc[4][2]) {
 }
 
 __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
-    __shared__ unsigned short buf0[PAD_ELEMS];
-    __shared__ unsigned short buf1[PAD_ELEMS];
-    __shared__ unsigned short wt[9 * NC * NC];
+    __shared__ uint4 buf0_4[PAD_ELEMS / 8];  // 16-byte aligned for the vector LDS reads
+    __shared__ uint4 buf1_4[PAD_ELEMS / 8];
+    unsigned short* const buf0 = (unsigned short*)buf0_4;
+    unsigned short* const buf1 = (unsigned short*)buf1_4;
+    __shared__ uint4 wt4[9 * NC * NC / 8];
+    unsigned short* const wt = (unsigned short*)wt4;
     __shared__ float red[16 * NC];
     __shared__ float gsum[NC];
     const int b = (int)blockIdx.x;
@@ -244,7 +260,7 @@ __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
     float vals[4][2][4];
 
     load_input(a.x + (long long)b * 3 * 256, buf0);
-    load_weights(p + CNN_OFF_W1, 3, 32, wt);
+    copy_weights(a.wt, 32, wt);
     zero_lds(buf1, PAD_ELEMS);
     __syncthreads();
     zero_acc(acc);
@@ -252,7 +268,7 @@ __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
     relu_store(acc, p + CNN_OFF_B1, buf1, act, vals, wave, lane);
     __syncthreads();
 
-    load_weights(p + CNN_OFF_W2, NC, 9 * NC, wt);
+    copy_weights(a.wt + 32 * NC, 9 * NC, wt);
     zero_lds(buf0, PAD_ELEMS);
     __syncthreads();
     zero_acc(acc);
@@ -260,7 +276,7 @@ __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
     relu_store(acc, p + CNN_OFF_B2, buf0, act ? act + 256 * NC : nullptr, vals, wave, lane);
     __syncthreads();
 
-    load_weights(p + CNN_OFF_W3, NC, 9 * NC, wt);
+    copy_weights(a.wt + (32 + 288) * NC, 9 * NC, wt);
     __syncthreads();
     zero_acc(acc);
     conv_fwd<NC, NC>(buf0, wt, acc, wave, lane);
@@ -280,9 +296,12 @@ __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
 // Backward of one image given the saved activations; writes the image's
 // parameter gradients (all but w4, b4) into partial[b][*].
 __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
-    __shared__ unsigned short bufx[PAD_ELEMS];
-    __shared__ unsigned short bufd[PAD_ELEMS];
-    __shared__ unsigned short wt[9 * NC * NC];
+    __shared__ uint4 bufx_4[PAD_ELEMS / 8];  // 16-byte aligned for the vector LDS reads
+    __shared__ uint4 bufd_4[PAD_ELEMS / 8];
+    unsigned short* const bufx = (unsigned short*)bufx_4;
+    unsigned short* const bufd = (unsigned short*)bufd_4;
+    __shared__ uint4 wt4[9 * NC * NC / 8];
+    unsigned short* const wt = (unsigned short*)wt4;
     __shared__ float red[16 * NC];
     __shared__ float dsum[NC];
     __shared__ float dg[NC];
@@ -299,7 +318,7 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
 
     // ---- layer 3: dZ3 = mask(a3) * dG / 256
     load_act(act + 256 * NC, bufx);  // a2, input of layer 3
-    load_weights(p + CNN_OFF_W3, NC, 9 * NC, wt);
+    copy_weights(a.wt + (32 + 288) * NC, 9 * NC, wt);
     zero_lds(bufd, PAD_ELEMS);
     __syncthreads();
     float vals[4][2][4];
@@ -337,7 +356,7 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
     channel_sum(vals, red, dsum, wave, lane);
     if (threadIdx.x < NC) part[CNN_OFF_B2 + threadIdx.x] = dsum[threadIdx.x];
     load_act(act, bufx);  // a1 (load_act zeroes then fills; its first barrier orders the reuse)
-    load_weights(p + CNN_OFF_W2, NC, 9 * NC, wt);
+    copy_weights(a.wt + 32 * NC, 9 * NC, wt);
     __syncthreads();
     conv_wgrad<NC, NC>(bufd, bufx, part + CNN_OFF_W2, wave, lane);
     zero_acc(acc);
@@ -459,6 +478,9 @@ __global__ __launch_bounds__(256) void features_kernel(FeatureArgs a) {
 }
 
 hipError_t launch_cnn_forward(const CnnArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(cnn_stage_weights_kernel, dim3((CNN_WT_ELEMS + 255) / 256), dim3(256), 0, st, a.params, a.wt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cnn_forward_kernel, dim3(a.batch), dim3(256), 0, st, a);
     return hipGetLastError();
 }

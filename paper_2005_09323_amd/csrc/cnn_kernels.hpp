@@ -22,7 +22,10 @@ struct CnnArgs {
     float* partial;       // [batch][CNN_N_PARAMS]
     float* grads;         // [CNN_N_PARAMS]
     float* loss;          // [1] or null
+    unsigned short* wt;   // BF16 weight tables [layer][kp][32], kp = 32, 288, 288 (staged once per call)
 };
+
+constexpr int CNN_WT_ELEMS = (32 + 288 + 288) * 32;  // the three staged weight tables
 
 struct AdamArgs {
     float* params;
