@@ -259,8 +259,8 @@ int lbm_set_open_channel(lbm_ctx* ctx, const lbm_open_channel* oc);
  * step in on-chip memory, so the populations cross HBM once per two steps.
  * They apply when every member's width is a multiple of 256; otherwise, and
  * for the last step of an odd batch, the library steps with shape 0.  Shape
- * 20, the default, is shape 16 while the active members give at least two
- * 256-column strips per compute unit and shape 0 otherwise (the few members
+ * 20, the default, is shape 16 while the active members give at least one
+ * 256-column strip per compute unit and shape 0 otherwise (the few members
  * an AMS branch re-simulates would leave most compute units idle).
  */
 int lbm_set_tile(lbm_ctx* ctx, int32_t tile_id);

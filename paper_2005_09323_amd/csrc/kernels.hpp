@@ -80,7 +80,7 @@ struct TileShape {
     int r;      // rows per wave (a tile is 256 columns by tyt * r rows); 1 for two-step shapes
     int xcd;    // 1: remap workgroups so each XCD gets a contiguous range of tiles
     int steps;  // lattice steps per launch: 1, or 2 (a strip of 256 columns swept bottom to top)
-    int adaptive;  // two-step shape used only while the active members give 2 strips per CU
+    int adaptive;  // two-step shape used only while the active members give a strip per CU
 };
 
 extern const TileShape TILE_SHAPES[];
