@@ -290,9 +290,15 @@ def train_score(flow, n: int, rounds: int, horizon: int, out=None, seed: int = 7
     pv = torch.cat([net.forward(x[val[i:i + batch]].contiguous()) for i in range(0, n_val, batch)])
     yv = ys[val]
     r2 = 1.0 - float(((pv - yv) ** 2).mean().item()) / float(yv.var().item())
+    # the plain score as a predictor of the same label: the mean drag over the `horizon` steps
+    # before the snapshot (the previous round's label), best linear fit, all rounds but the first
+    lab = torch.stack(labels).double().cpu().numpy()      # [rounds, n]
+    prev, nxt = lab[:-1].ravel(), lab[1:].ravel()
+    slope, icpt = np.polyfit(prev, nxt, 1)
+    r2_plain = 1.0 - float(((slope * prev + icpt - nxt) ** 2).mean()) / float(nxt.var())
     _emit(out, {"experiment": "score_training", "samples": n_tot, "horizon": horizon, "epochs": epochs,
                 "adam_steps": steps, "train_wall_s": train_wall, "validation_r2": r2,
-                "label_mean": mu, "label_std": sd})
+                "plain_score_r2": r2_plain, "label_mean": mu, "label_std": sd})
     return net, mu, sd, fargs
 
 
@@ -436,7 +442,7 @@ def open_channel_stats(flow: OpenFlow, n: int, burn: int, steps: int, out=None, 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["gktl", "ams", "all", "open"])
+    ap.add_argument("which", choices=["gktl", "ams", "all", "open", "score"])
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--repeats", type=int, default=10)
     ap.add_argument("--flow", choices=["channel", "open"], default="channel",
@@ -467,6 +473,8 @@ def main(argv=None):
                     z=args.ams_z, direct_steps=args.direct_steps)
     if args.which == "open":
         open_channel_stats(OpenFlow(), args.n, args.open_burn, args.open_steps, out=args.out)
+    if args.which == "score":  # the learned score's training and its prediction against the plain score
+        train_score(flow, args.ams_n, args.rounds, 512, out=args.out)
 
 
 if __name__ == "__main__":
