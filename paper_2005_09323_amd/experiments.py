@@ -244,7 +244,8 @@ def gktl_and_direct(flow, n: int, repeats: int, ks, out=None, seed: int = 100,
 
 def train_score(flow, n: int, rounds: int, horizon: int, out=None, seed: int = 7, epochs: int = 8):
     """(snapshot, mean drag over the next `horizon` steps) pairs from the ensemble itself, then
-    Adam on the device network.  Returns (net, label mean, label std, feature args)."""
+    Adam on the device network.  Returns (net, label mean, label std, feature args, record): the
+    record holds the validation R^2 and that of the plain score as a predictor of the same labels."""
     src = burn_in(flow, n, seed, cap=horizon + 2)
     x0, y0, s = flow.square
     fargs = dict(px0=x0 + s, py0=y0 + s // 2 - 32, patch=64, pool=4, u_scale=20.0, rho_scale=200.0)
@@ -296,10 +297,11 @@ def train_score(flow, n: int, rounds: int, horizon: int, out=None, seed: int = 7
     prev, nxt = lab[:-1].ravel(), lab[1:].ravel()
     slope, icpt = np.polyfit(prev, nxt, 1)
     r2_plain = 1.0 - float(((slope * prev + icpt - nxt) ** 2).mean()) / float(nxt.var())
-    _emit(out, {"experiment": "score_training", "samples": n_tot, "horizon": horizon, "epochs": epochs,
-                "adam_steps": steps, "train_wall_s": train_wall, "validation_r2": r2,
-                "plain_score_r2": r2_plain, "label_mean": mu, "label_std": sd})
-    return net, mu, sd, fargs
+    rec = {"experiment": "score_training", "samples": n_tot, "horizon": horizon, "epochs": epochs,
+           "adam_steps": steps, "train_wall_s": train_wall, "validation_r2": r2,
+           "plain_score_r2": r2_plain, "label_mean": mu, "label_std": sd}
+    _emit(out, rec)
+    return net, mu, sd, fargs, rec
 
 
 def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: int = 512,
@@ -308,7 +310,7 @@ def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: i
     """AMS with the plain score (the running window mean of the drag) and with the learned score,
     for the event max over [0, T_a] of the `window`-step mean drag >= mu + z sigma_window.  Each run
     stops once every trajectory has reached that level, so the estimate is for that level only."""
-    net, lab_mu, lab_sd, fargs = train_score(flow, n, rounds, window, out=out)
+    net, lab_mu, lab_sd, fargs, _ = train_score(flow, n, rounds, window, out=out)
     src = burn_in(flow, n, seed, cap=max(40_002, direct_steps + 2))
     t0 = _sync_time()
     st = drag_stats(src, 20_000, windows=(window,))

@@ -164,3 +164,14 @@ def test_features_match_oracle():
         f[:, olbm.solid_mask(ch)] = 0
         ref = ofeat.near_wake(ch, f, px0, py0, 64, 4, 20.0, 200.0)
         assert np.abs(got[i] - ref).max() <= 1e-6 * np.abs(ref).max() + 1e-9
+
+
+def test_learned_score_predicts_future_drag_better_than_plain_score():
+    """What the trained network gains over the method without it: on the stationary channel flow
+    (128 members of 512 x 128 after the burn-in), the network's validation R^2 for the next
+    512-step mean drag exceeds that of the plain score (the previous 512-step mean, best linear
+    fit).  About 20 s on one MI355X."""
+    from paper_2005_09323_amd import experiments
+    _, _, _, _, rec = experiments.train_score(experiments.Flow(), 128, 100, 512, epochs=16)
+    print(rec)
+    assert rec["validation_r2"] > rec["plain_score_r2"] + 0.05
