@@ -104,23 +104,30 @@ __global__ __launch_bounds__(1024) void ams_select_kernel(AmsArgs a) {
         *a.n_killed = n_killed;
         *a.level = level;
     }
-    for (int j = t; j < n_killed; j += nt) {
+    // one wave per kill: its parent, and the parent's first crossing found 64
+    // samples at a time (a wave-wide vote per block of samples)
+    const int wave = t >> 6, lane = t & 63, nwaves = nt >> 6;
+    for (int j = wave; j < n_killed; j += nwaves) {
         if (n_surv == 0) {  // extinction: nothing to branch from
-            a.parent[j] = -1;
-            a.branch_t[j] = -1;
+            if (lane == 0) {
+                a.parent[j] = -1;
+                a.branch_t[j] = -1;
+            }
             continue;
         }
         const U64x4 w = philox4x64_10((uint64_t)j, (uint64_t)a.iteration, 0, 0, a.key, PURPOSE_AMSP);
         const int p = surv[(int)index_below(w.v[0], (uint64_t)n_surv)];
-        a.parent[j] = p;
         const float* row = a.series + (long long)p * a.t_len;
         int tb = -1;
-        for (int tt = 0; tt < a.t_len; ++tt)
-            if (row[tt] > level) {
-                tb = tt;
-                break;
-            }
-        a.branch_t[j] = tb;
+        for (int t0 = 0; t0 < a.t_len && tb < 0; t0 += 64) {
+            const int tt = t0 + lane;
+            const unsigned long long hits = __ballot(tt < a.t_len && row[tt] > level);
+            if (hits) tb = t0 + __ffsll(hits) - 1;
+        }
+        if (lane == 0) {
+            a.parent[j] = p;
+            a.branch_t[j] = tb;
+        }
     }
 }
 
