@@ -348,7 +348,8 @@ int ams_score_kill_branch(const float* series_dev, int32_t n, int32_t t_len, int
  * Window mean of each member's drag series (paper Section 3.2, time-averaged
  * drag): out_dev[m][t] = (1/T) sum_{t' = t-T+1}^{t} f_d(t') for t >= T-1 within
  * [0, t_len) of the device series (float[n][ld]), and -inf for t < T-1.
- * Sums in FP64.  Used as the plain AMS score.
+ * Sums in FP64 (each thread sums its first window in order and slides over
+ * its next 15 outputs).  Used as the plain AMS score.
  */
 int lbm_window_mean(const float* series_dev, int32_t n, int32_t ld, int32_t t_len, int32_t window,
                     float* out_dev, void* hip_stream);

@@ -1,6 +1,7 @@
 // State copies (checkpoints) and the window-mean score of the drag series.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "../../include/lbm.h"
@@ -35,19 +36,37 @@ namespace lbm {
 // One block per member; thread t owns output columns t, t + blockDim, ...
 // Each window sum is formed afresh in FP64 (T adds), so every column is
 // independent of the others' rounding.
-__global__ void window_mean_kernel(const float* series, int ld, int t_len, int window, float* out) {
-    const int m = (int)blockIdx.x;
-    const float* row = series + (long long)m * ld;
-    float* orow = out + (long long)m * t_len;
+// Each thread owns WM_RUN consecutive outputs: the first window is summed in
+// order (FP64), the others slide (+ the new sample, - the oldest), so a row
+// costs about t_len (window / WM_RUN + 1) loads instead of t_len window; the
+// FP64 sliding error (a few ulps of the running sum) is far below the FP32
+// output rounding.
+constexpr int WM_RUN = 16;
+
+__global__ __launch_bounds__(256) void window_mean_kernel(const float* series, int n, int ld, int t_len, int window,
+                                                          float* out) {
+    const long long t0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * WM_RUN;
+    if (t0 >= t_len) return;
+    const int t1 = (int)min((long long)t_len, t0 + WM_RUN);
     const double inv = 1.0 / (double)window;
-    for (int t = (int)threadIdx.x; t < t_len; t += (int)blockDim.x) {
-        if (t < window - 1) {
-            orow[t] = -INFINITY;
-            continue;
-        }
+    for (int m = (int)blockIdx.y; m < n; m += (int)gridDim.y) {  // rows beyond the grid's height
+        const float* row = series + (long long)m * ld;
+        float* orow = out + (long long)m * t_len;
         double acc = 0.0;
-        for (int k = t - window + 1; k <= t; ++k) acc += (double)row[k];
-        orow[t] = (float)(acc * inv);
+        bool have = false;
+        for (int t = (int)t0; t < t1; ++t) {
+            if (t < window - 1) {
+                orow[t] = -INFINITY;
+                continue;
+            }
+            if (!have) {
+                for (int k = t - window + 1; k <= t; ++k) acc += (double)row[k];
+                have = true;
+            } else {
+                acc += (double)row[t] - (double)row[t - window];
+            }
+            orow[t] = (float)(acc * inv);
+        }
     }
 }
 
@@ -58,8 +77,9 @@ extern "C" int lbm_window_mean(const float* series_dev, int32_t n, int32_t ld, i
     if (!series_dev || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
     if (n < 0 || t_len < 0 || ld < t_len || window < 1) return lbm_fail(LBM_EINVAL, "bad sizes");
     if (n == 0 || t_len == 0) return LBM_OK;
-    hipLaunchKernelGGL(window_mean_kernel, dim3(n), dim3(256), 0, (hipStream_t)hip_stream, series_dev, ld, t_len,
-                       window, out_dev);
+    const unsigned runs = (unsigned)((t_len + WM_RUN - 1) / WM_RUN);
+    hipLaunchKernelGGL(window_mean_kernel, dim3((runs + 255) / 256, (unsigned)std::min(n, 65535)), dim3(256), 0,
+                       (hipStream_t)hip_stream, series_dev, n, ld, t_len, window, out_dev);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "window mean kernel");
 }
