@@ -166,6 +166,11 @@ int lbm_set_time(lbm_ctx* ctx, int32_t t);
    member's drag has become non-finite since lbm_init. */
 int lbm_flags(const lbm_ctx* ctx, int32_t* out_dev);
 
+/* Overwrite the non-finite flags from flags_dev (device int32[n_members],
+   non-zero = flagged); used to resume a saved ensemble exactly.  Enqueued on
+   the context's stream; flags_dev must stay valid until the copy has run. */
+int lbm_set_flags(lbm_ctx* ctx, const int32_t* flags_dev);
+
 /*
  * Pressure, stress and shear on the square's faces, for the populations the
  * next step collides (paper Section 2.1: the drag as the surface integral of

@@ -562,6 +562,12 @@ extern "C" int lbm_flags(const lbm_ctx* c, int32_t* out_dev) {
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "flags copy");
 }
 
+extern "C" int lbm_set_flags(lbm_ctx* c, const int32_t* flags_dev) {
+    if (!c || !flags_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(c->d_flags, flags_dev, sizeof(int) * c->n, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "flags copy");
+}
+
 extern "C" int lbm_set_collision(lbm_ctx* c, int32_t model, double s_bulk, double s_third, double s_fourth) {
     if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     if (model != 0 && model != 1) return lbm_fail(LBM_EINVAL, "collision model %d: 0 (BGK) or 1 (central moments)", model);

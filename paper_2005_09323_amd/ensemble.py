@@ -8,7 +8,8 @@ unless stated otherwise.
 from __future__ import annotations
 
 import ctypes
-from typing import Optional, Sequence
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
 
 import torch
 
@@ -22,6 +23,20 @@ def _ptr(t: Optional[torch.Tensor]):
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass(frozen=True)
+class MemberSpec:
+    """One trajectory's lattice: nx x ny cells, BGK time tau, body force along x, and the
+    square obstacle as (x0, y0, side) of its lower-left solid cell (None: no obstacle)."""
+    nx: int
+    ny: int
+    tau: float
+    force_x: float
+    square: Optional[Tuple[int, int, int]]
+
+
+CHECKPOINT_VERSION = 1
 
 
 class Ensemble:
@@ -55,6 +70,11 @@ class Ensemble:
         for m in self.members:
             self.offsets.append(off)
             off += 9 * m.nx * m.ny
+        # the settings a checkpoint must carry to resume the same dynamics
+        self._collision = ("bgk", 1.0, 1.0, 1.0)
+        self._open = None
+        self._observable = (0.0, 1.0, 1.0)
+        self._active = None
 
     # -- lifetime -----------------------------------------------------------
     def close(self) -> None:
@@ -80,13 +100,17 @@ class Ensemble:
 
     def set_observable(self, mu: float, sigma: float, dt: float) -> None:
         native.check(self.lib.lbm_set_observable(self._ctx, mu, sigma, dt))
+        self._observable = (float(mu), float(sigma), float(dt))
 
     def set_active(self, active: Optional[Sequence[int]]) -> None:
         if active is None:
             native.check(self.lib.lbm_set_active(self._ctx, None))
+            self._active = None
             return
-        arr = (ctypes.c_int32 * self.n)(*[int(bool(a)) for a in active])
+        flags = [int(bool(a)) for a in active]
+        arr = (ctypes.c_int32 * self.n)(*flags)
         native.check(self.lib.lbm_set_active(self._ctx, arr))
+        self._active = flags
 
     def set_tile(self, tile_id: int) -> None:
         native.check(self.lib.lbm_set_tile(self._ctx, tile_id))
@@ -103,15 +127,18 @@ class Ensemble:
         """'bgk' (default) or 'central' (central-moment relaxation with the given rates); before init."""
         code = {"bgk": 0, "central": 1}[model]
         native.check(self.lib.lbm_set_collision(self._ctx, code, s_bulk, s_third, s_fourth))
+        self._collision = (model, float(s_bulk), float(s_third), float(s_fourth))
 
     def set_open_channel(self, u_c: Optional[float], grid_x0: int = 0, grid_bar: int = 0,
                          sponge_x0: int = 1 << 30, sponge_tau: float = 1.0) -> None:
         """Inlet, entrance grid, sponge and outlet instead of periodic x (None: periodic); before init."""
         if u_c is None:
             native.check(self.lib.lbm_set_open_channel(self._ctx, None))
+            self._open = None
             return
         oc = native.OpenChannelDesc(u_c, grid_x0, grid_bar, sponge_x0, 0, sponge_tau)
         native.check(self.lib.lbm_set_open_channel(self._ctx, ctypes.byref(oc)))
+        self._open = (float(u_c), int(grid_x0), int(grid_bar), int(sponge_x0), float(sponge_tau))
 
     def set_graphs(self, on: bool) -> None:
         """Replay full 64-step chunks from a captured HIP graph (default) or launch every kernel."""
@@ -167,6 +194,65 @@ class Ensemble:
 
     def copy_state_in(self, m: int, src: torch.Tensor, t: int) -> None:
         native.check(self.lib.lbm_copy_state_in(self._ctx, m, _ptr(src), t))
+
+    # -- checkpoint / resume -----------------------------------------------
+    def checkpoint(self) -> dict:
+        """Everything that decides the ensemble's future, as host tensors and plain values
+        (synchronises): each member's state and time, the drag series, the FP64 observable
+        integrals, the non-finite flags, the active mask, and the settings (collision, open channel, observable).
+        The selection and perturbation draws need no saved state: they are counter-based,
+        keyed by (key, period)."""
+        torch.cuda.synchronize(self.device)
+        states = torch.cat([self.state(m).reshape(-1) for m in range(self.n)]).cpu()
+        return {
+            "version": CHECKPOINT_VERSION,
+            "members": [(int(m.nx), int(m.ny), float(m.tau), float(m.force_x),
+                         None if m.square is None else tuple(int(v) for v in m.square)) for m in self.members],
+            "capacity": int(self.capacity),
+            "states": states,
+            "times": torch.tensor([self.time(m) for m in range(self.n)], dtype=torch.int32),
+            "series": self.series.cpu(),
+            "accum": self.accum.cpu(),
+            "flags": self.flags().cpu(),
+            "active": None if self._active is None else list(self._active),
+            "collision": self._collision,
+            "open": self._open,
+            "observable": self._observable,
+        }
+
+    @classmethod
+    def restore(cls, ckpt: dict, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None) -> "Ensemble":
+        """A new ensemble that continues exactly where `ckpt` (from `checkpoint`) left off."""
+        if ckpt.get("version") != CHECKPOINT_VERSION:
+            raise ValueError(f"checkpoint version {ckpt.get('version')} (expected {CHECKPOINT_VERSION})")
+        members = [MemberSpec(nx, ny, tau, fx, None if sq is None else tuple(sq))
+                   for nx, ny, tau, fx, sq in ckpt["members"]]
+        ens = cls(members, ckpt["capacity"], device=device, stream=stream)
+        model, sb, s3, s4 = ckpt["collision"]
+        ens.set_collision(model, sb, s3, s4)
+        if ckpt["open"] is not None:
+            ens.set_open_channel(*ckpt["open"])
+        ens.set_observable(*ckpt["observable"])
+        ens.set_active(ckpt["active"])
+        states = ckpt["states"].to(ens.device)
+        times = ckpt["times"].tolist()
+        for m in range(ens.n):
+            o, mm = ens.offsets[m], ens.members[m]
+            ens.copy_state_in(m, states[o:o + 9 * mm.nx * mm.ny], times[m])
+        ens.series.copy_(ckpt["series"])
+        ens.accum.copy_(ckpt["accum"])
+        flags = ckpt["flags"].to(device=ens.device, dtype=torch.int32).contiguous()
+        native.check(ens.lib.lbm_set_flags(ens._ctx, _ptr(flags)))
+        torch.cuda.synchronize(ens.device)  # the staging copy of the states must outlive the copies
+        return ens
+
+    def save(self, path: str) -> None:
+        torch.save(self.checkpoint(), path)
+
+    @classmethod
+    def load(cls, path: str, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None) -> "Ensemble":
+        """Read a checkpoint written by `save` (plain tensors and values only) and restore it."""
+        return cls.restore(torch.load(path, map_location="cpu", weights_only=True), device=device, stream=stream)
 
     # -- rare-event selection ----------------------------------------------
     def gktl_select_clone(self, k: float, key: int, period: int, eps: float = 0.0,

@@ -58,6 +58,7 @@ _SIG = {
     "lbm_member_time": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),
     "lbm_set_time": (ctypes.c_int, [_P, _I]),
     "lbm_flags": (ctypes.c_int, [_P, _P]),
+    "lbm_set_flags": (ctypes.c_int, [_P, _P]),
     "lbm_set_tile": (ctypes.c_int, [_P, _I]),
     "lbm_tile_count": (_I, []),
     "lbm_face_diagnostics": (ctypes.c_int, [_P, _P]),

@@ -38,13 +38,27 @@ class GktlRun:
         """lambda(k) = (1/T_a) sum_i ln R_i, T_a in the units of dt."""
         return float(self.ln_r.double().sum().item()) / (self.t_a * dt)
 
+    def then(self, later: "GktlRun") -> "GktlRun":
+        """This run followed by `later`, its continuation (same k and tau, its periods numbered on
+        from this run's, its drag columns right after this run's): one record of the whole run."""
+        if later.k != self.k or later.tau != self.tau:
+            raise ValueError("a continuation needs the same k and tau")
+        if later.col0 != self.col0 + self.t_a:
+            raise ValueError("the continuation must start at the column this run ended on")
+        return GktlRun(self.k, self.tau, self.n_periods + later.n_periods, self.col0,
+                       torch.cat([self.ancestors, later.ancestors]), torch.cat([self.integrals, later.integrals]),
+                       torch.cat([self.ln_r, later.ln_r]))
+
 
 def run_gktl(ens: Ensemble, k: float, n_periods: int, tau: int, key: int, eps: float = 0.0,
-             snapshots: Optional[torch.Tensor] = None) -> GktlRun:
+             snapshots: Optional[torch.Tensor] = None, first_period: int = 0) -> GktlRun:
     """GKTL over n_periods cloning periods of tau steps, selecting at every t_i = i tau (T_a included).
 
     The ensemble must be initialised and its observable set (lbm_set_observable);
-    its drag series needs tau * n_periods free columns.
+    its drag series needs tau * n_periods free columns.  first_period numbers the
+    periods (the selection and perturbation draws are keyed by it): a run resumed
+    from a checkpoint taken after p periods continues with first_period = p, and
+    `GktlRun.then` joins the two records.
     """
     n = ens.n
     dev = ens.device
@@ -57,7 +71,7 @@ def run_gktl(ens: Ensemble, k: float, n_periods: int, tau: int, key: int, eps: f
     for i in range(n_periods):
         ens.step(tau)
         ints[i].copy_(ens.accum)  # the period integrals, before the selection resets them
-        native.check(lib.gktl_select_clone(ens._ctx, k, key, i, eps, _ptr(snapshots), n_snap,
+        native.check(lib.gktl_select_clone(ens._ctx, k, key, first_period + i, eps, _ptr(snapshots), n_snap,
                                            ctypes.c_void_p(anc[i].data_ptr()), ctypes.c_void_p(lnr[i:].data_ptr())))
     return GktlRun(k, tau, n_periods, col0, anc, ints, lnr)
 
