@@ -263,10 +263,15 @@ int lbm_set_open_channel(lbm_ctx* ctx, const lbm_open_channel* oc);
  * of 256 columns from the bottom row to the top and keeps the intermediate
  * step in on-chip memory, so the populations cross HBM once per two steps.
  * They apply when every member's width is a multiple of 256; otherwise, and
- * for the last step of an odd batch, the library steps with shape 0.  Shape
- * 20, the default, is shape 16 while the active members give at least one
- * 256-column strip per compute unit and shape 0 otherwise (the few members
- * an AMS branch re-simulates would leave most compute units idle).
+ * for the last step of an odd batch, the library steps with shape 0.  Shapes
+ * 21-23 are shape 16 with each strip cut into workgroups of 128, 64 and 32
+ * rows (the rows next to a cut are collided by both neighbours).  Shape 20,
+ * the default, makes two steps per launch with whole strips when there are
+ * at least two per compute unit and with strips cut into the tallest row
+ * ranges that give four workgroups per compute unit otherwise (32 rows at
+ * the least); it steps with shape 0 while the active members give fewer
+ * than 1.5 workgroups per compute unit (the few members an AMS branch
+ * re-simulates would leave most compute units idle).
  */
 int lbm_set_tile(lbm_ctx* ctx, int32_t tile_id);
 int32_t lbm_tile_count(void);

@@ -91,6 +91,7 @@ struct lbm_ctx {
     lbm::Segment seg[lbm::MAX_SEGMENTS];
     // two-step launches (when the chosen shape has two steps and every member qualifies)
     bool two_step = false;
+    bool split2 = false;  // some strip of the two-step table is split into row ranges
     int nseg2 = 0;
     int total_blocks2 = 0;
     lbm::Segment seg2[lbm::MAX_SEGMENTS];

@@ -15,7 +15,7 @@ struct Segment {
     int tiles_per_member;  // tiles_x * tiles_y
     int tiles_x;           // tiles of 256 columns
     int vec;               // 1: width a multiple of 4, rows handled four cells per lane
-    int pad_;
+    int rows;              // two-step strips: rows per workgroup (the lattice height when not split)
 };
 
 struct StepArgs {
@@ -34,6 +34,8 @@ struct StepArgs {
     // non-null: the launch covers only these members (all of seg[0]'s shape),
     // tiles_per_member workgroups each, in list order
     const int* active_list;
+    // two-step launches: 1 when some strip is split into row ranges (Segment::rows)
+    int split;
     // non-null: open channels; the outlet ghost columns [member][9][ny]
     // (MemberDev::ghost_off), filled for this step by the ghost kernel
     const float* ghost;
@@ -81,6 +83,8 @@ struct TileShape {
     int xcd;    // 1: remap workgroups so each XCD gets a contiguous range of tiles
     int steps;  // lattice steps per launch: 1, or 2 (a strip of 256 columns swept bottom to top)
     int adaptive;  // two-step shape used only while the active members give a strip per CU
+    int seg_rows;  // two-step shapes: rows per workgroup (0: whole strips; -1: split only when
+                   // the strips alone leave workgroup slots empty)
 };
 
 extern const TileShape TILE_SHAPES[];

@@ -107,18 +107,46 @@ static int validate_member(const lbm_member_desc& d, int i) {
     return LBM_OK;
 }
 
+// Rows per workgroup of a two-step shape's strips (0: whole strips).  The
+// adaptive shape keeps whole strips when there are at least as many as
+// workgroup slots (two per compute unit); otherwise it cuts them into the
+// tallest row ranges (128, 64 or 32 rows) that give two workgroups per slot,
+// or 32 rows when none does.  A few tall strips leave most slots idle, and a
+// cut costs only the rows that both neighbours collide at phase A.  Measured
+// on 16 to 96 members of 1024 x 256 and 64 to 128 of 512 x 128, this comes
+// within 5 % of the best row range, at 1.2 to 1.9 x the speed of whole strips.
+static int strip_rows(const lbm_ctx* c, const TileShape& ts) {
+    if (ts.seg_rows >= 0) return ts.seg_rows;
+    const long long slots = 2LL * c->cu_count;
+    auto groups = [&](int h) {
+        long long g = 0;
+        for (int m = 0; m < c->n; ++m) {
+            const auto& d = c->desc[m];
+            const int rows = h > 0 ? std::min(h, d.ny) : d.ny;
+            g += (long long)(d.nx / 256) * ((d.ny + rows - 1) / rows);
+        }
+        return g;
+    };
+    if (groups(0) >= slots) return 0;
+    for (int h : {128, 64})
+        if (groups(h) >= 2 * slots) return h;
+    return 32;
+}
+
 // Segment table of one tiling: runs of consecutive members with the same
 // lattice shape share it.  strips: the two-step kernel's tiling (one
 // workgroup per 256-column strip, all rows).
 static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* seg, int& nseg, int& total) {
     const int rows = ts.tyt * ts.r;
+    const int split = strips ? strip_rows(c, ts) : 0;
     nseg = 0;
     int blocks = 0;
     for (int m = 0; m < c->n; ++m) {
         const auto& d = c->desc[m];
         const bool same = nseg > 0 && c->desc[seg[nseg - 1].member_begin].nx == d.nx &&
                           c->desc[seg[nseg - 1].member_begin].ny == d.ny;
-        const int tx = (d.nx + 255) / 256, ty = strips ? 1 : (d.ny + rows - 1) / rows;
+        const int hseg = split > 0 ? std::min(split, d.ny) : d.ny;  // strips: rows per workgroup
+        const int tx = (d.nx + 255) / 256, ty = strips ? (d.ny + hseg - 1) / hseg : (d.ny + rows - 1) / rows;
         if (!same) {
             if (nseg == MAX_SEGMENTS)
                 return lbm_fail(LBM_EUNSUPPORTED, "more than %d runs of distinct lattice shapes; group members by shape",
@@ -130,7 +158,7 @@ static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* se
             s.tiles_x = tx;
             // four cells per lane needs 16-byte rows, and 32-bit byte offsets over the member's block
             s.vec = (d.nx % 4 == 0 && 36LL * d.nx * d.ny < (1LL << 31)) ? 1 : 0;
-            s.pad_ = 0;
+            s.rows = strips ? hseg : 0;
             seg[nseg++] = s;
         }
         if ((long long)blocks + (long long)tx * ty > (1LL << 31) - 1)
@@ -142,20 +170,22 @@ static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* se
 }
 
 // Whether the next batch makes two steps per launch.  The two-step kernel
-// gives one workgroup per 256-column strip and sweeps all rows: with few
-// active members (an AMS branch re-simulates a handful) that leaves most
-// compute units idle, and one-step launches (many small tiles, the same
-// results bit for bit) are faster.  The adaptive shape uses it only with at
-// least one active strip per compute unit (measured on 1024 x 256 members:
-// 0.85 x the one-step speed at 0.75 strips per CU, 1.1 x at 1, 1.34 x at 1.5,
-// 1.57 x at 2).
+// gives one workgroup per strip (or row range of a strip): with few active
+// members (an AMS branch re-simulates a handful) that leaves most compute
+// units idle, and one-step launches (many small tiles, the same results bit
+// for bit) are faster.  The adaptive shape uses it once the active members
+// give 1.5 workgroups per compute unit (measured with split strips: 0.8 x the
+// one-step speed at 1 workgroup per CU, 1.1 x at 1.5, 1.2 to 1.5 x at 2).
 static bool two_step_now(const lbm_ctx* c) {
     if (!c->two_step) return false;
     if (!TILE_SHAPES[c->tile_id].adaptive) return true;
-    long long strips = 0;
-    for (int m = 0; m < c->n; ++m)
-        if (c->h_active[m]) strips += c->desc[m].nx / 256;
-    return strips >= (long long)c->cu_count;
+    long long groups = 0;  // workgroups of the active members
+    for (int s = 0; s < c->nseg2; ++s) {
+        const int end = s + 1 < c->nseg2 ? c->seg2[s + 1].member_begin : c->n;
+        for (int m = c->seg2[s].member_begin; m < end; ++m)
+            if (c->h_active[m]) groups += c->seg2[s].tiles_per_member;
+    }
+    return 2 * groups >= 3LL * c->cu_count;
 }
 
 // Tables of the current tile shape.  A two-step shape applies when every
@@ -175,6 +205,9 @@ static int build_segments(lbm_ctx* c) {
             int rc = build_table(c, ts, true, c->seg2, c->nseg2, c->total_blocks2);
             if (rc) return rc;
             c->two_step = true;
+            c->split2 = false;
+            for (int s = 0; s < c->nseg2; ++s)
+                c->split2 = c->split2 || c->seg2[s].rows < c->desc[c->seg2[s].member_begin].ny;
         }
     }
     return build_table(c, TILE_SHAPES[c->one_tile], false, c->seg, c->nseg, c->total_blocks);
@@ -403,12 +436,14 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
     a.pop1 = c->pop[1];
     a.partial = c->d_partial;
     a.xcd = TILE_SHAPES[c->one_tile].xcd;
+    a.split = 0;
     a.total_blocks = c->total_blocks;
     a.nseg = c->nseg;
     for (int s = 0; s < c->nseg; ++s) a.seg[s] = c->seg[s];
     StepArgs a2 = a;
     if (c->two_step) {
         a2.xcd = TILE_SHAPES[c->tile_id].xcd;
+        a2.split = c->split2 ? 1 : 0;
         a2.total_blocks = c->total_blocks2;
         a2.nseg = c->nseg2;
         for (int s = 0; s < c->nseg2; ++s) a2.seg[s] = c->seg2[s];
@@ -706,6 +741,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         if (ts.adaptive) continue;                    // a policy over shapes 16 and 0, not a shape
         const bool two = ts.steps == 2;
         a.total_blocks = two ? c->total_blocks2 : c->total_blocks;
+        a.split = two && c->split2 ? 1 : 0;
         a.xcd = ts.xcd;
         a.nseg = two ? c->nseg2 : c->nseg;
         for (int s = 0; s < a.nseg; ++s) a.seg[s] = two ? c->seg2[s] : c->seg[s];

@@ -291,13 +291,14 @@ __device__ __forceinline__ unsigned square_links(const MemberDev& m, int x, int 
 
 // Workgroup -> (member, tile): members are grouped in segments of equal
 // lattice shape; within a segment tiles run x-fastest, then y, then member.
-__device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx, int& ty, int& vec) {
+__device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx, int& ty, int& vec, int& rows) {
     if (a.active_list) {  // a subset of members of one lattice shape
         const int k = b / a.seg[0].tiles_per_member;
         const int tile = b - k * a.seg[0].tiles_per_member;
         ty = tile / a.seg[0].tiles_x;
         tx = tile - ty * a.seg[0].tiles_x;
         vec = a.seg[0].vec;
+        rows = a.seg[0].rows;
         return a.active_list[k];
     }
     int s = 0;
@@ -309,6 +310,7 @@ __device__ __forceinline__ int block_to_member(const StepArgs& a, int b, int& tx
     ty = tile / a.seg[s].tiles_x;
     tx = tile - ty * a.seg[s].tiles_x;
     vec = a.seg[s].vec;
+    rows = a.seg[s].rows;
     return a.seg[s].member_begin + mloc;
 }
 

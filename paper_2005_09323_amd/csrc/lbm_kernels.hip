@@ -209,8 +209,8 @@ __device__ __forceinline__ void vec_row(const MemberDev& m, const float* __restr
 template <int TYT, int R, int MODEL, bool OPEN>
 __global__ __launch_bounds__(64 * TYT) __attribute__((amdgpu_waves_per_eu(R == 1 && MODEL == 0 && !OPEN ? 5 : 4))) void step_kernel(StepArgs a) {
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
-    int tx, ty, vec;
-    const int mi = block_to_member(a, b, tx, ty, vec);
+    int tx, ty, vec, seg_rows;
+    const int mi = block_to_member(a, b, tx, ty, vec, seg_rows);
     // the three bookkeeping reads are independent: issue them together
     const int on = a.active[mi];
     const MemberDev m = a.members[mi];
@@ -389,7 +389,7 @@ const TileShape TILE_SHAPES[] = {
     {4, 1, 0, 1, 0}, {4, 2, 0, 1, 0}, {8, 1, 0, 1, 0}, {2, 2, 0, 1, 0},
     {16, 1, 0, 1, 0}, {1, 4, 0, 1, 0}, {4, 4, 0, 1, 0}, {8, 2, 0, 1, 0},
     {4, 1, 1, 2, 0}, {2, 1, 1, 2, 0}, {8, 1, 1, 2, 0}, {4, 1, 0, 2, 0},
-    {4, 1, 1, 2, 1},
+    {4, 1, 1, 2, 1, -1}, {4, 1, 1, 2, 0, 128}, {4, 1, 1, 2, 0, 64}, {4, 1, 1, 2, 0, 32},
 };
 const int N_TILE_SHAPES = (int)(sizeof(TILE_SHAPES) / sizeof(TILE_SHAPES[0]));
 

@@ -115,7 +115,7 @@ __device__ __forceinline__ void collide_row(const MemberDev& m, f4 p[9], double*
 // hold every row still needed for NW <= 8.
 constexpr int VROWS = 16;
 
-template <int NW, int MODEL, bool OPEN>
+template <int NW, int MODEL, bool OPEN, bool SPLIT>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void step2_kernel(StepArgs a) {
     constexpr int LAG = OPEN ? 2 : 1;          // phase B works on row y - LAG
     constexpr int RROWS = NW + 1 + LAG;        // ring rows: y - LAG - 1 .. y for the whole workgroup
@@ -123,8 +123,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     __shared__ OutletVel vring[OPEN ? VROWS : 1];
     float* const ring = (float*)ring4;
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
-    int tx, ty, vec;
-    const int mi = block_to_member(a, b, tx, ty, vec);
+    int tx, ty, vec, seg_rows;
+    const int mi = block_to_member(a, b, tx, ty, vec, seg_rows);
     const int on = a.active[mi];
     const MemberDev m = a.members[mi];
     const int par = a.parity[mi] ^ a.flip;
@@ -182,18 +182,26 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     auto solid = [&](int dx, int yy, int j, bool near, unsigned g3) {
         return (near && in_square(m, x0 + dx, yy)) || (OPEN && ((gcols >> (dx + 1)) & (g3 >> j) & 1u));
     };
-    const int iters = (ny + LAG - 1) / NW + 1;      // phase B of the last iteration reaches row ny - 1
+    // rows [ya, yb) of the strip are this workgroup's to write; phase A also
+    // collides the LAG rows on either side that phase B (and the outlet's
+    // velocity ring) pull from, which the neighbouring workgroups of a split
+    // strip collide too, bit for bit the same
+    // (SPLIT = false: whole strips, compiled without the row-range arithmetic)
+    const int ya = SPLIT ? ty * seg_rows : 0, yb = SPLIT ? min(ya + seg_rows, ny) : ny;
+    const int ya0 = SPLIT ? max(ya - LAG, 0) : 0, ya1 = SPLIT ? min(yb + LAG, ny) : ny;  // phase A rows
+    // phase B of the last iteration reaches row yb - 1
+    const int iters = SPLIT ? (yb + LAG - ya0 + NW - 1) / NW : (ny + LAG - 1) / NW + 1;
     RowLoads cur;
-    if (wv < ny) load_row<OPEN>(m, rs, voff, xl, xr, wv, cur, ghost, left_end, right_end);
+    if ((SPLIT ? ya0 + wv : wv) < ya1) load_row<OPEN>(m, rs, voff, xl, xr, ya0 + wv, cur, ghost, left_end, right_end);
 #pragma unroll 1
     for (int j = 0; j < iters; ++j) {
-        const int y = j * NW + wv;
+        const int y = ya0 + j * NW + wv;
         // phase A: row y at step t+1 into the ring.  Every gather this row
         // needs (the outside cell, the obstacle's bounce-back words) is
         // issued before the prefetch of the wave's next row: waits on memory
         // complete in issue order, so waiting for them leaves the prefetch in
         // flight.
-        const bool row_a = y < ny;
+        const bool row_a = y < ya1;
         const bool near_sq = row_a && sq_cols && y >= m.sy0 - 1 && y <= m.sy0 + m.ss;
         const unsigned gA = row_a ? rows3(y) : 0u;
         const bool near_a = near_sq || gA != 0u;
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
         }
         RowLoads nxt;
-        if (y + NW < ny) load_row<OPEN>(m, rs, voff, xl, xr, y + NW, nxt, ghost, left_end, right_end);
+        if (y + NW < ya1) load_row<OPEN>(m, rs, voff, xl, xr, y + NW, nxt, ghost, left_end, right_end);
         if (row_a) {
             float* row = ring + (y % RROWS) * 9 * RING_ROW;
             collide_row<MODEL, OPEN>(m, p, part0, near_sq, x0, y, sponge);
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         lds_barrier();
         // phase B: row y - LAG at step t+2 from the ring to the other buffer
         const int r = y - LAG;
-        if (r >= 0 && r < ny) {
+        if (r >= ya && r < yb) {
             const float* own = ring + (r % RROWS) * 9 * RING_ROW;
             const bool near_sq = sq_cols && r >= m.sy0 - 1 && r <= m.sy0 + m.ss;
             const unsigned gB = rows3(r);
@@ -363,16 +371,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     }
 }
 
-template <int NW>
-static hipError_t launch_step2_t(const StepArgs& a, int model, hipStream_t st) {
+template <int NW, bool SPLIT>
+static void launch_step2_s(const StepArgs& a, int model, hipStream_t st) {
     const dim3 grid(a.total_blocks), block(64 * NW);
     if (a.ghost) {
-        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((step2_kernel<NW, 0, true>), grid, block, 0, st, a);
+        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, true, SPLIT>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((step2_kernel<NW, 0, true, SPLIT>), grid, block, 0, st, a);
     } else {
-        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, false>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((step2_kernel<NW, 0, false>), grid, block, 0, st, a);
+        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, false, SPLIT>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((step2_kernel<NW, 0, false, SPLIT>), grid, block, 0, st, a);
     }
+}
+
+template <int NW>
+static hipError_t launch_step2_t(const StepArgs& a, int model, hipStream_t st) {
+    if (a.split) launch_step2_s<NW, true>(a, model, st);
+    else launch_step2_s<NW, false>(a, model, st);
     return hipGetLastError();
 }
 

@@ -100,15 +100,19 @@ def test_ragged_mixed_shapes_all_tiles():
 def _two_step_tiles():
     from paper_2005_09323_amd import native
     lib = native.lib()
-    return [t for t in range(16, min(20, lib.lbm_tile_count()))]  # 20 is the adaptive default
+    # 20 is the adaptive default; 21-23 split every strip into workgroups of 128, 64 and 32 rows
+    return [t for t in range(16, lib.lbm_tile_count()) if t != 20]
 
 
 def test_two_step_shapes_bit_identical_to_one_step():
     """Widths that are multiples of 256: the two-step kernel (every shape) against shape 0, bit for bit.
 
     Squares straddling a strip boundary and next to the periodic edges, a lattice lower than
-    the rows per iteration, and an odd step count (chunks that end with a single step)."""
+    the rows per iteration, and an odd step count (chunks that end with a single step); strips
+    split into row ranges, with a square across the seams at rows 64 and 128."""
     members = [workloads.Member(256, 37, 0.6, 2e-5, (50, 10, 6)),
+               workloads.Member(256, 150, 0.57, 2e-5, (100, 60, 8)),
+               workloads.Member(256, 150, 0.57, 2e-5, (200, 124, 8)),
                workloads.Member(512, 21, 0.53, 1e-5, (253, 8, 6)),
                workloads.Member(256, 12, 0.56, 3e-5, (1, 1, 3)),
                workloads.Member(256, 12, 0.56, 3e-5, (251, 7, 4)),

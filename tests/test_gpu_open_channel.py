@@ -92,7 +92,7 @@ def test_open_channel_tiles_bit_identical():
         torch.cuda.synchronize()
         runs.append((ens.drag(0, steps).cpu().numpy(), [ens.state(i).cpu().numpy().copy() for i in range(2)]))
         ens.close()
-    assert native.lib().lbm_tile_count() == 21
+    assert native.lib().lbm_tile_count() == 24
     d0, s0 = runs[0]
     for i, m in enumerate(MEMBERS):
         fluid = ~olbm.solid_mask(_channel(m, OPEN))
@@ -276,10 +276,10 @@ def test_open_channel_two_step_bit_identical_to_one_step(collision):
     steps = 151
     for mem, o in ((members, op), (single, op_single), (straddle, op_straddle)):
         runs = {}
-        for tile in (0, 16, 17, 18, 19, 20):
+        for tile in (0, 16, 17, 18, 19, 20, 21, 22, 23):  # 21-23: strips split into 128, 64, 32 rows
             ens = _ensemble(mem, steps + 40, o, collision, tile=tile)
             ens.init(41, 1e-3)
-            if tile in (16, 17, 18, 19):
+            if tile in (16, 17, 18, 19, 21, 22, 23):
                 assert ens.launch_steps() == 2
             ens.step(steps - 1)
             if len(mem) > 2:
