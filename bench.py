@@ -249,6 +249,37 @@ def _grid_cells(m, op) -> int:
     return b * sum(1 for y in range(b // 2, m.ny) if (y - b // 2) % (2 * b) < b) if b > 0 else 0
 
 
+def score_scaling(batches) -> None:
+    """Score network forward and training step (forward, backward, reduction, Adam) against the
+    batch size: one JSON line per batch, BF16 matrix-core TFLOP/s of the convolutions."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2005_09323_amd.ensemble import ScoreNet
+
+    torch.cuda.set_device(0)
+    p = workloads.cnn_params(1)
+    flat = np.concatenate([np.ravel(p[k]) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4")])
+    flop_fwd = 256 * 32 * 2 * (27 + 288 + 288)            # per picture, convolutions only
+    flop_train = flop_fwd + 256 * 32 * 2 * (288 + 288) + 256 * 32 * 2 * (27 + 288 + 288)
+    for b in batches:
+        net = ScoreNet(torch.from_numpy(flat.astype(np.float32)), b)
+        xb, lb = workloads.cnn_batch(b, 2)
+        xt = torch.from_numpy(xb.astype(np.float32)).cuda()
+        lt = torch.from_numpy(lb.astype(np.float32)).cuda()
+        net.train_step(xt, lt)
+        t_fwd = _timed(lambda: net.forward(xt), 20)
+        t_train = _timed(lambda: net.train_step(xt, lt), 20)
+        print(json.dumps({"batch": b, "ms_forward": round(t_fwd, 4), "ms_train_step": round(t_train, 4),
+                          "mfma_TFLOPs_forward": round(b * flop_fwd / (t_fwd / 1e3) / 1e12, 1),
+                          "mfma_TFLOPs_train": round(b * flop_train / (t_train / 1e3) / 1e12, 1),
+                          "frac_of_bf16_peak_forward": round(b * flop_fwd / (t_fwd / 1e3) / 2.5e15, 4)}),
+              flush=True)
+        del net, xt, lt
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,8 +290,9 @@ def main():
                     help="lattice launch shape (-1: autotune; 16, two steps per launch, is the profiled default)")
     ap.add_argument("--cpu-steps", type=int, default=800, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_ensemble1024_traffic.json"))
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
-                    help="copy: time a plain device copy of --copy-mib MiB (counter calibration)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "score-scaling"],
+                    help="copy: time a plain device copy of --copy-mib MiB (counter calibration); "
+                         "score-scaling: the score network against the batch size")
     ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--no-legs", action="store_true", help="skip the GKTL / AMS / score-network legs")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "central"],
@@ -268,6 +300,8 @@ def main():
     args = ap.parse_args()
     if args.mode == "copy":
         return copy_calibration(args.copy_mib, max(args.steps, 1))
+    if args.mode == "score-scaling":
+        return score_scaling([256, 1024, 4096, 16384, 65536])
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build"}))
         sys.exit(2)

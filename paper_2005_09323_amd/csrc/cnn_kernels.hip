@@ -22,7 +22,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NC = 32;   // channels of every hidden layer
 constexpr int PADW = 18; // padded image side
-constexpr int PAD_ELEMS = PADW * PADW * NC;
+// LDS rows are padded so that the sixteen lanes of a fragment, one pixel (or
+// weight row) apart, fall on distinct banks: 32 channels at a stride of 36
+constexpr int TS = 36;   // elements per pixel of a 32-channel activation tile
+constexpr int WS = 36;   // elements per row of a staged weight table
+constexpr int PAD_ELEMS = PADW * PADW * TS;
 
 // FP32 -> BF16, round to nearest even (NaN stays NaN).
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -62,15 +66,17 @@ __global__ __launch_bounds__(256) void cnn_stage_weights_kernel(const float* __r
     wt[e] = f2bf(v);
 }
 
-// One staged table (kp rows) into LDS with 16-byte copies.
+// One staged table (kp rows of 32) into LDS rows of WS elements, 8-byte copies.
 __device__ void copy_weights(const unsigned short* __restrict__ src, int kp, unsigned short* wt) {
-    const uint4* s4 = (const uint4*)src;
-    uint4* d4 = (uint4*)wt;
-    for (int e = (int)threadIdx.x; e < kp * NC / 8; e += (int)blockDim.x) d4[e] = s4[e];
+    const uint2* s2 = (const uint2*)src;
+    uint2* d2 = (uint2*)wt;
+    for (int e = (int)threadIdx.x; e < kp * NC / 4; e += (int)blockDim.x) d2[(e >> 3) * (WS / 4) + (e & 7)] = s2[e];
 }
 
+// n elements (a multiple of 8, 16-byte aligned) set to zero with 16-byte stores.
 __device__ void zero_lds(unsigned short* p, int n) {
-    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) p[e] = 0;
+    uint4* p4 = (uint4*)p;
+    for (int e = (int)threadIdx.x; e < n / 8; e += (int)blockDim.x) p4[e] = uint4{0u, 0u, 0u, 0u};
 }
 
 // acc[mt][nt] += conv of the padded input: output pixel (y = 4 wave + mt,
@@ -85,7 +91,7 @@ __device__ void conv_fwd(const unsigned short* in, const unsigned short* wt, f32
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bfr[nt][j] = (short)wt[(ks * 16 + kq + j) * NC + nt * 16 + col];
+            for (int j = 0; j < 4; ++j) bfr[nt][j] = (short)wt[(ks * 16 + kq + j) * WS + nt * 16 + col];
         int tap[4], ch[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -128,12 +134,12 @@ __device__ void conv_dgrad(const unsigned short* dz, const unsigned short* wt, f
         const int o0 = ks * 16 + kq - tap0 * NC;  // the lane's 4 consecutive output channels
         bf16x4 bfr[2];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) bfr[nt] = *(const bf16x4*)(wt + (tap0 * NC + nt * 16 + col) * NC + o0);
+        for (int nt = 0; nt < 2; ++nt) bfr[nt] = *(const bf16x4*)(wt + (tap0 * NC + nt * 16 + col) * WS + o0);
         const int dy = tap0 / 3, dx = tap0 - 3 * (tap0 / 3);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int y = wave * 4 + mt;
-            const bf16x4 afr = *(const bf16x4*)(dz + ((y - dy + 2) * PADW + (col - dx + 2)) * NC + o0);
+            const bf16x4 afr = *(const bf16x4*)(dz + ((y - dy + 2) * PADW + (col - dx + 2)) * TS + o0);
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(afr, bfr[nt], acc[mt][nt]);
         }
@@ -160,7 +166,7 @@ __device__ void conv_wgrad(const unsigned short* dz, const unsigned short* xin, 
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int px = kq + j;
-                afr[j] = (short)dz[((py + 1) * PADW + (px + 1)) * NC + ot * 16 + col];
+                afr[j] = (short)dz[((py + 1) * PADW + (px + 1)) * TS + ot * 16 + col];
                 bfr[j] = kk < K ? (short)xin[((py + dy) * PADW + (px + dx)) * CSTRIDE + c] : (short)0;
             }
             acc = mfma16(afr, bfr, acc);
@@ -211,7 +217,7 @@ __device__ void load_act(const unsigned short* __restrict__ act, unsigned short*
     __syncthreads();
     for (int e = (int)threadIdx.x; e < 256 * NC; e += (int)blockDim.x) {
         const int p = e / NC, c = e - p * NC, y = p / 16, xx = p - y * 16;
-        buf[((y + 1) * PADW + (xx + 1)) * NC + c] = act[e];
+        buf[((y + 1) * PADW + (xx + 1)) * TS + c] = act[e];
     }
 }
 
@@ -230,7 +236,7 @@ __device__ void relu_store(f32x4 acc[4][2], const float* __restrict__ bias, unsi
                 const float a = fmaxf(acc[mt][nt][j] + bias[o], 0.0f);
                 vals[mt][nt][j] = a;
                 const unsigned short b = f2bf(a);
-                if (tile) tile[((y + 1) * PADW + (x + 1)) * NC + o] = b;
+                if (tile) tile[((y + 1) * PADW + (x + 1)) * TS + o] = b;
                 if (act) act[(y * 16 + x) * NC + o] = b;
             }
 }
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
     __shared__ uint4 buf1_4[PAD_ELEMS / 8];
     unsigned short* const buf0 = (unsigned short*)buf0_4;
     unsigned short* const buf1 = (unsigned short*)buf1_4;
-    __shared__ uint4 wt4[9 * NC * NC / 8];
+    __shared__ uint4 wt4[9 * NC * WS / 8];
     unsigned short* const wt = (unsigned short*)wt4;
     __shared__ float red[16 * NC];
     __shared__ float gsum[NC];
@@ -272,14 +278,14 @@ __global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
     zero_lds(buf0, PAD_ELEMS);
     __syncthreads();
     zero_acc(acc);
-    conv_fwd<NC, NC>(buf1, wt, acc, wave, lane);
+    conv_fwd<NC, TS>(buf1, wt, acc, wave, lane);
     relu_store(acc, p + CNN_OFF_B2, buf0, act ? act + 256 * NC : nullptr, vals, wave, lane);
     __syncthreads();
 
     copy_weights(a.wt + (32 + 288) * NC, 9 * NC, wt);
     __syncthreads();
     zero_acc(acc);
-    conv_fwd<NC, NC>(buf0, wt, acc, wave, lane);
+    conv_fwd<NC, TS>(buf0, wt, acc, wave, lane);
     relu_store(acc, p + CNN_OFF_B3, nullptr, act ? act + 2 * 256 * NC : nullptr, vals, wave, lane);
     channel_sum(vals, red, gsum, wave, lane);
     if (threadIdx.x == 0) {
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
     __shared__ uint4 bufd_4[PAD_ELEMS / 8];
     unsigned short* const bufx = (unsigned short*)bufx_4;
     unsigned short* const bufd = (unsigned short*)bufd_4;
-    __shared__ uint4 wt4[9 * NC * NC / 8];
+    __shared__ uint4 wt4[9 * NC * WS / 8];
     unsigned short* const wt = (unsigned short*)wt4;
     __shared__ float red[16 * NC];
     __shared__ float dsum[NC];
@@ -332,11 +338,11 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
                 const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
                 const float d = bf2f(a3[(y * 16 + x) * NC + o]) > 0.0f ? dg[o] : 0.0f;
                 vals[mt][nt][j] = d;
-                bufd[((y + 1) * PADW + (x + 1)) * NC + o] = f2bf(d);
+                bufd[((y + 1) * PADW + (x + 1)) * TS + o] = f2bf(d);
             }
     channel_sum(vals, red, dsum, wave, lane);  // includes the barrier before dZ3 is read
     if (threadIdx.x < NC) part[CNN_OFF_B3 + threadIdx.x] = dsum[threadIdx.x];
-    conv_wgrad<NC, NC>(bufd, bufx, part + CNN_OFF_W3, wave, lane);
+    conv_wgrad<NC, TS>(bufd, bufx, part + CNN_OFF_W3, wave, lane);
     f32x4 acc[4][2];
     zero_acc(acc);
     conv_dgrad(bufd, wt, acc, wave, lane);
@@ -349,16 +355,16 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
-                const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * NC + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
+                const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * TS + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
                 vals[mt][nt][j] = d;
-                bufd[((y + 1) * PADW + (x + 1)) * NC + o] = f2bf(d);
+                bufd[((y + 1) * PADW + (x + 1)) * TS + o] = f2bf(d);
             }
     channel_sum(vals, red, dsum, wave, lane);
     if (threadIdx.x < NC) part[CNN_OFF_B2 + threadIdx.x] = dsum[threadIdx.x];
     load_act(act, bufx);  // a1 (load_act zeroes then fills; its first barrier orders the reuse)
     copy_weights(a.wt + 32 * NC, 9 * NC, wt);
     __syncthreads();
-    conv_wgrad<NC, NC>(bufd, bufx, part + CNN_OFF_W2, wave, lane);
+    conv_wgrad<NC, TS>(bufd, bufx, part + CNN_OFF_W2, wave, lane);
     zero_acc(acc);
     conv_dgrad(bufd, wt, acc, wave, lane);
     __syncthreads();
@@ -370,9 +376,9 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
-                const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * NC + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
+                const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * TS + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
                 vals[mt][nt][j] = d;
-                bufd[((y + 1) * PADW + (x + 1)) * NC + o] = f2bf(d);
+                bufd[((y + 1) * PADW + (x + 1)) * TS + o] = f2bf(d);
             }
     channel_sum(vals, red, dsum, wave, lane);
     if (threadIdx.x < NC) part[CNN_OFF_B1 + threadIdx.x] = dsum[threadIdx.x];
