@@ -388,16 +388,23 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
 }
 
 // Gradients summed over the batch in a fixed order, in two passes: pass 1
-// sums each chunk of RED_CHUNK images in image order (the read-out's own
-// gradients w4, b4 from the saved averages) into the chunk's first partial
-// row, pass 2 sums those rows in chunk order and, in its first workgroup,
-// the loss (a fixed-order tree).  Deterministic for a given batch size.
-constexpr int RED_CHUNK = 64;
+// sums each chunk of images in image order (the read-out's own gradients w4,
+// b4 from the saved averages) into the chunk's first partial row, pass 2
+// sums those rows in chunk order and, in its first workgroup, the loss (a
+// fixed-order tree).  Deterministic for a given batch size.  Chunks hold
+// about sqrt(batch) images (a power of two, 8 to 256), so that neither pass
+// runs a long chain of dependent loads: 16 images at a batch of 256.
+__host__ __device__ inline int red_chunk(int batch) {
+    int c = 8;
+    while (c < 256 && c * c < batch) c *= 2;
+    return c;
+}
 
 __global__ __launch_bounds__(256) void cnn_reduce_chunks_kernel(CnnArgs a) {
     const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q >= CNN_N_PARAMS) return;
-    const int b0 = (int)blockIdx.y * RED_CHUNK, b1 = min(b0 + RED_CHUNK, a.batch);
+    const int rc = red_chunk(a.batch);
+    const int b0 = (int)blockIdx.y * rc, b1 = min(b0 + rc, a.batch);
     float tot = 0.0f;
     if (q >= CNN_OFF_W4) {
         for (int b = b0; b < b1; ++b) {
@@ -412,10 +419,11 @@ __global__ __launch_bounds__(256) void cnn_reduce_chunks_kernel(CnnArgs a) {
 
 __global__ __launch_bounds__(256) void cnn_reduce_final_kernel(CnnArgs a) {
     const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int chunks = (a.batch + RED_CHUNK - 1) / RED_CHUNK;
+    const int rc = red_chunk(a.batch);
+    const int chunks = (a.batch + rc - 1) / rc;
     if (q < CNN_N_PARAMS) {
         float tot = 0.0f;
-        for (int c = 0; c < chunks; ++c) tot += a.partial[(long long)c * RED_CHUNK * CNN_N_PARAMS + q];
+        for (int c = 0; c < chunks; ++c) tot += a.partial[(long long)c * rc * CNN_N_PARAMS + q];
         a.grads[q] = tot;
     }
     if (blockIdx.x == 0 && a.loss) {  // the whole first workgroup
@@ -494,7 +502,8 @@ hipError_t launch_cnn_backward(const CnnArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(cnn_backward_kernel, dim3(a.batch), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned cols = (CNN_N_PARAMS + 255) / 256, chunks = (unsigned)((a.batch + RED_CHUNK - 1) / RED_CHUNK);
+    const unsigned cols = (CNN_N_PARAMS + 255) / 256;
+    const unsigned chunks = (unsigned)((a.batch + red_chunk(a.batch) - 1) / red_chunk(a.batch));
     hipLaunchKernelGGL(cnn_reduce_chunks_kernel, dim3(cols, chunks), dim3(256), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cnn_reduce_final_kernel, dim3(cols), dim3(256), 0, st, a);
