@@ -27,6 +27,7 @@ constexpr int PADW = 18; // padded image side
 constexpr int TS = 36;   // elements per pixel of a 32-channel activation tile
 constexpr int WS = 36;   // elements per row of a staged weight table
 constexpr int PAD_ELEMS = PADW * PADW * TS;
+constexpr int DZT = 260; // elements per channel of a channel-major dZ copy (256 pixels, padded)
 
 // FP32 -> BF16, round to nearest even (NaN stays NaN).
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -148,8 +149,10 @@ __device__ void conv_dgrad(const unsigned short* dz, const unsigned short* wt, f
 
 // Weight gradient of one image: dW[o][c][tap] = sum_p dZ[p][o] X[p + tap - 1][c],
 // a GEMM over the 256 pixels; written (not added) to out in canonical order.
+// dZ comes channel-major (dzt[o * DZT + p], unpadded pixels): a lane's four
+// consecutive pixels of one channel are one 8-byte read.
 template <int CIN, int CSTRIDE>
-__device__ void conv_wgrad(const unsigned short* dz, const unsigned short* xin, float* __restrict__ out, int wave,
+__device__ void conv_wgrad(const unsigned short* dzt, const unsigned short* xin, float* __restrict__ out, int wave,
                            int lane) {
     constexpr int K = 9 * CIN;
     constexpr int KP = (K + 15) / 16 * 16;
@@ -162,11 +165,11 @@ __device__ void conv_wgrad(const unsigned short* dz, const unsigned short* xin, 
         const int dy = tap / 3, dx = tap - 3 * (tap / 3);
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int py = 0; py < 16; ++py) {
-            bf16x4 afr, bfr;
+            const bf16x4 afr = *(const bf16x4*)(dzt + (ot * 16 + col) * DZT + py * 16 + kq);
+            bf16x4 bfr;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int px = kq + j;
-                afr[j] = (short)dz[((py + 1) * PADW + (px + 1)) * TS + ot * 16 + col];
                 bfr[j] = kk < K ? (short)xin[((py + dy) * PADW + (px + dx)) * CSTRIDE + c] : (short)0;
             }
             acc = mfma16(afr, bfr, acc);
@@ -342,11 +345,25 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
             }
     channel_sum(vals, red, dsum, wave, lane);  // includes the barrier before dZ3 is read
     if (threadIdx.x < NC) part[CNN_OFF_B3 + threadIdx.x] = dsum[threadIdx.x];
-    conv_wgrad<NC, TS>(bufd, bufx, part + CNN_OFF_W3, wave, lane);
+    // dZ channel-major for the weight gradient, in the weight table's space once
+    // the data gradient has read the table
+    auto write_dzt = [&]() {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    wt[(nt * 16 + col) * DZT + (wave * 4 + mt) * 16 + kq + j] = f2bf(vals[mt][nt][j]);
+    };
     f32x4 acc[4][2];
     zero_acc(acc);
     conv_dgrad(bufd, wt, acc, wave, lane);
     __syncthreads();
+    write_dzt();
+    __syncthreads();
+    conv_wgrad<NC, TS>(wt, bufx, part + CNN_OFF_W3, wave, lane);
+    __syncthreads();  // dZ3 and a2 are read
     // ---- layer 2: dZ2 = mask(a2) * dA2
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -361,14 +378,17 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
             }
     channel_sum(vals, red, dsum, wave, lane);
     if (threadIdx.x < NC) part[CNN_OFF_B2 + threadIdx.x] = dsum[threadIdx.x];
-    load_act(act, bufx);  // a1 (load_act zeroes then fills; its first barrier orders the reuse)
     copy_weights(a.wt + 32 * NC, 9 * NC, wt);
     __syncthreads();
-    conv_wgrad<NC, TS>(bufd, bufx, part + CNN_OFF_W2, wave, lane);
     zero_acc(acc);
     conv_dgrad(bufd, wt, acc, wave, lane);
     __syncthreads();
-    // ---- layer 1: dZ1 = mask(a1) * dA1
+    write_dzt();
+    load_act(act, bufx);  // a1 (load_act zeroes then fills; its first barrier orders the reuse)
+    __syncthreads();
+    conv_wgrad<NC, TS>(wt, bufx, part + CNN_OFF_W2, wave, lane);
+    __syncthreads();  // dZ2 and a1's tile are read by the weight gradient
+    // ---- layer 1: dZ1 = mask(a1) * dA1, only its weight gradient left (no data gradient)
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -378,13 +398,13 @@ __global__ __launch_bounds__(256) void cnn_backward_kernel(CnnArgs a) {
                 const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
                 const float d = bf2f(bufx[((y + 1) * PADW + (x + 1)) * TS + o]) > 0.0f ? acc[mt][nt][j] : 0.0f;
                 vals[mt][nt][j] = d;
-                bufd[((y + 1) * PADW + (x + 1)) * TS + o] = f2bf(d);
             }
-    channel_sum(vals, red, dsum, wave, lane);
+    write_dzt();
+    channel_sum(vals, red, dsum, wave, lane);  // its barriers order dZ1 before the weight gradient
     if (threadIdx.x < NC) part[CNN_OFF_B1 + threadIdx.x] = dsum[threadIdx.x];
     load_input(a.x + (long long)b * 3 * 256, bufx);
     __syncthreads();
-    conv_wgrad<3, 4>(bufd, bufx, part + CNN_OFF_W1, wave, lane);
+    conv_wgrad<3, 4>(wt, bufx, part + CNN_OFF_W1, wave, lane);
 }
 
 // Gradients summed over the batch in a fixed order, in two passes: pass 1
