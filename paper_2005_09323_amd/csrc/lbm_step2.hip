@@ -240,7 +240,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
             if (near_a) {
+                // the row's own populations at t for the bounce-back: the rows of the
+                // +-x movers are row y already; the other six, one coalesced load each
                 const unsigned rowoff = (unsigned)y * (unsigned)nx;
+                f4 ownv[9];
+#pragma unroll
+                for (int i = 1; i < 9; ++i)
+                    ownv[i] = CY[OPP[i]] == 0 ? cur.v[OPP[i]]
+                                              : __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * ((unsigned)OPP[i] * plane + rowoff), 0);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (solid(k, y, 1, near_sq, gA)) continue;  // a solid cell's results are never stored
@@ -248,8 +255,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     for (int i = 1; i < 9; ++i) {
                         const int ys = y - CY[i];
                         if (ys < 0 || ys >= ny) continue;
-                        if (solid(k - CX[i], ys, 1 - CY[i], near_sq, gA))
-                            p[i][k] = src[(unsigned)OPP[i] * plane + rowoff + (unsigned)(x0 + k)];
+                        if (solid(k - CX[i], ys, 1 - CY[i], near_sq, gA)) p[i][k] = ownv[i][k];
                     }
                 }
             }
