@@ -135,7 +135,7 @@ static int strip_rows(const lbm_ctx* c, const TileShape& ts) {
 
 // Segment table of one tiling: runs of consecutive members with the same
 // lattice shape share it.  strips: the two-step kernel's tiling (one
-// workgroup per 256-column strip, all rows).
+// workgroup per 256-column strip, or per row range of one: Segment::rows).
 static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* seg, int& nseg, int& total) {
     const int rows = ts.tyt * ts.r;
     const int split = strips ? strip_rows(c, ts) : 0;
