@@ -456,3 +456,36 @@ def test_autotune_table_is_reused(tmp_path):
     ens.step(3)
     assert int(ens.flags().sum()) == 0
     ens.close()
+
+
+def test_adaptive_shape_cuts_strips_for_a_mid_sized_batch():
+    """32 members of 1024 x 256 give 128 whole strips, too few for the device: the default shape
+    cuts them into row ranges and still makes two steps per launch; 8 of them active fall back to
+    one step.  Every state and drag value equals those of the one-step shape 0."""
+    m = workloads.Member(1024, 256, 0.51, 2e-6, (240, 112, 32))
+    runs = []
+    for tile in (None, 0):
+        ens = _ensemble([m] * 32, 80)
+        if tile is not None:
+            ens.set_tile(tile)
+        ens.init(3, 1e-3)
+        if tile is None:
+            assert ens.launch_steps() == 2
+        ens.step(37)
+        ens.set_active([1] * 8 + [0] * 24)
+        if tile is None:
+            assert ens.launch_steps() == 1
+        ens.step(5)
+        ens.set_active(None)
+        ens.step(30)
+        torch.cuda.synchronize()
+        runs.append(([ens.time(i) for i in (0, 8)], ens.drag(0, 73).cpu().numpy(),
+                     [ens.state(i).cpu().numpy().copy() for i in (0, 13, 31)]))
+        ens.close()
+        torch.cuda.empty_cache()
+    (t0, d0, s0), (t1, d1, s1) = runs
+    assert t0 == t1 == [73, 68]
+    assert np.array_equal(d0[:8], d1[:8]) and np.array_equal(d0[8:, :68], d1[8:, :68])
+    fluid = ~olbm.solid_mask(_channel(m))
+    for a, b in zip(s0, s1):
+        assert np.array_equal(a[:, fluid], b[:, fluid])
