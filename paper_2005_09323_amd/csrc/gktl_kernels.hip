@@ -139,10 +139,17 @@ __global__ __launch_bounds__(256) void mass_partial_kernel(MassArgs a) {
     double acc = 0.0;
     if (b0 < total) {
         const long long e1 = min(b0 + MASS_CHUNK, total);
-        for (long long e = b0 + threadIdx.x; e < e1; e += 256) {
-            const long long cell = e % plane;
-            const int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
+        long long e = b0 + threadIdx.x;
+        // the cell of the first element by division, the next ones by stepping 256 cells on
+        const long long cell = e % plane;
+        int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
+        for (; e < e1; e += 256) {
             if (!in_solid(m, x, y)) acc += (double)base[e];
+            x += 256;
+            while (x >= m.nx) {
+                x -= m.nx;
+                if (++y == m.ny) y = 0;
+            }
         }
     }
     sh[threadIdx.x] = acc;
