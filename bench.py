@@ -303,7 +303,7 @@ def main():
     if args.mode == "score-scaling":
         return score_scaling([256, 1024, 4096, 16384, 65536])
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the library has no multi-GPU path"}))
         sys.exit(2)
 
     import torch

@@ -16,7 +16,7 @@ What is computed, and where the paper states it:
 * halfway bounce-back no-slip on the channel walls and on the square
   (Section 2, boundary conditions);
 * a uniform body force density F = (g_x, 0) replaces the paper's inlet (the
-  periodic, force-driven channel is the workload of this build).  It enters
+  periodic, force-driven channel is the benchmark workload).  It enters
   by Guo's scheme: u = (sum f_i c_i + F/2)/rho in the equilibrium, and the
   source term (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F is
   added after relaxation;
