@@ -280,6 +280,44 @@ def score_scaling(batches) -> None:
         torch.cuda.empty_cache()
 
 
+def open_parts(steps: int = 256) -> None:
+    """Where the open channel's time goes: 1024 members of 512 x 128 with the square R = 16
+    at the centre, the two-step kernel, with parts of the open channel (entrance grid, sponge)
+    taken away and against periodic x.  One JSON line per variant, ms per lattice step."""
+    import torch
+
+    import workloads
+    from paper_2005_09323_amd.ensemble import Ensemble
+
+    torch.cuda.set_device(0)
+    sq = workloads.centred_square(256, 64, 16)
+    with_sq = workloads.Member(512, 128, 0.501, 0.0, sq)
+    no_sq = workloads.Member(512, 128, 0.501, 0.0, None)
+    full = (0.05, 32, 8, 447, 1.0)
+    variants = [("open, central moments", with_sq, full, True),
+                ("open, central moments, no grid", with_sq, (0.05, 32, 0, 447, 1.0), True),
+                ("open, central moments, no sponge", with_sq, (0.05, 32, 8, 1 << 30, 1.0), True),
+                ("open, BGK", with_sq, full, False),
+                ("periodic, central moments", with_sq, None, True),
+                ("periodic, central moments, no square", no_sq, None, True),
+                ("periodic, BGK", with_sq, None, False),
+                ("periodic, BGK, no square", no_sq, None, False)]
+    for name, m, op, central in variants:
+        ens = Ensemble([m] * 1024, series_capacity=2 * steps + 2)
+        ens.set_tile(20)
+        if central:
+            ens.set_collision("central", 1.0, 1.0, 1.0)
+        if op is not None:
+            ens.set_open_channel(*op)
+        ens.init(300, 1e-3)
+        ens.step(128)
+        ms = _timed(lambda: ens.step(steps)) / steps
+        print(json.dumps({"variant": name, "ms_per_step": round(ms, 4),
+                          "MLUPS_all_cells": round(1024 * m.nx * m.ny / (ms / 1e3) / 1e6),
+                          "nonfinite_members": int(ens.flags().sum())}), flush=True)
+        ens.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,9 +328,10 @@ def main():
                     help="lattice launch shape (-1: autotune; 16, two steps per launch, is the profiled default)")
     ap.add_argument("--cpu-steps", type=int, default=800, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_ensemble1024_traffic.json"))
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "score-scaling"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "score-scaling", "open-parts"],
                     help="copy: time a plain device copy of --copy-mib MiB (counter calibration); "
-                         "score-scaling: the score network against the batch size")
+                         "score-scaling: the score network against the batch size; "
+                         "open-parts: the open channel with parts taken away")
     ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--no-legs", action="store_true", help="skip the GKTL / AMS / score-network legs")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "central"],
@@ -302,6 +341,8 @@ def main():
         return copy_calibration(args.copy_mib, max(args.steps, 1))
     if args.mode == "score-scaling":
         return score_scaling([256, 1024, 4096, 16384, 65536])
+    if args.mode == "open-parts":
+        return open_parts()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the library has no multi-GPU path"}))
         sys.exit(2)
