@@ -177,10 +177,30 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     auto rows3 = [&](int yy) -> unsigned {
         return OPEN ? (grow(yy - 1) ? 1u : 0u) | (grow(yy) ? 2u : 0u) | (grow(yy + 1) ? 4u : 0u) : 0u;
     };
-    // solid test of column x0 + dx (dx = -1 .. 4) in row yy = row - 1 + j (0 <= yy < ny) of a
-    // row whose grid rows are g3; near: the row is near the square
-    auto solid = [&](int dx, int yy, int j, bool near, unsigned g3) {
-        return (near && in_square(m, x0 + dx, yy)) || (OPEN && ((gcols >> (dx + 1)) & (g3 >> j) & 1u));
+    // OPEN: bit j: column x0 - 1 + j (j = 0..5) crosses the square
+    unsigned sqcols = 0;
+    if (OPEN && sq_cols)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) sqcols |= ((unsigned)(x0 - 1 + j - m.sx0) < (unsigned)m.ss ? 1u : 0u) << j;
+    // OPEN: solid cells around the lane's four cells of row yy: bit 6 j + dx + 1 for column
+    // x0 + dx (dx = -1 .. 4) of row yy - 1 + j (j = 0..2), from the grid rows g3 of
+    // rows3(yy) and, if near (the row is near the square), the square's rows; built once
+    // per row so that each bounce-back test is one bit
+    auto solids = [&](int yy, bool near, unsigned g3) -> unsigned {
+        unsigned mk = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            unsigned row = ((g3 >> j) & 1u) ? gcols : 0u;
+            if (near && (unsigned)(yy - 1 + j - m.sy0) < (unsigned)m.ss) row |= sqcols;
+            mk |= row << (6 * j);
+        }
+        return mk;
+    };
+    // solid test of column x0 + dx in row yy = row - 1 + j: from the mask mk of the row
+    // (OPEN), or from the square's bounds if near (periodic x has only the square; the
+    // mask measured slower there)
+    auto solid = [&](unsigned mk, int dx, int yy, int j, bool near) {
+        return OPEN ? ((mk >> (6 * j + dx + 1)) & 1u) != 0u : near && in_square(m, x0 + dx, yy);
     };
     // rows [ya, yb) of the strip are this workgroup's to write; phase A also
     // collides the LAG rows on either side that phase B (and the outlet's
@@ -248,14 +268,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 for (int i = 1; i < 9; ++i)
                     ownv[i] = CY[OPP[i]] == 0 ? cur.v[OPP[i]]
                                               : __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * ((unsigned)OPP[i] * plane + rowoff), 0);
+                const unsigned mk = OPEN ? solids(y, near_sq, gA) : 0u;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (solid(k, y, 1, near_sq, gA)) continue;  // a solid cell's results are never stored
+                    if (solid(mk, k, y, 1, near_sq)) continue;  // a solid cell's results are never stored
 #pragma unroll
                     for (int i = 1; i < 9; ++i) {
                         const int ys = y - CY[i];
                         if (ys < 0 || ys >= ny) continue;
-                        if (solid(k - CX[i], ys, 1 - CY[i], near_sq, gA)) p[i][k] = ownv[i][k];
+                        if (solid(mk, k - CX[i], ys, 1 - CY[i], near_sq)) p[i][k] = ownv[i][k];
                     }
                 }
             }
@@ -310,6 +331,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const bool near_sq = sq_cols && r >= m.sy0 - 1 && r <= m.sy0 + m.ss;
             const unsigned gB = rows3(r);
             const bool near_b = near_sq || gB != 0u;
+            const unsigned mkb = OPEN && near_b ? solids(r, near_sq, gB) : 0u;
             f4 p[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -343,22 +365,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             if (near_b) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (solid(k, r, 1, near_sq, gB)) continue;
+                    if (solid(mkb, k, r, 1, near_sq)) continue;
 #pragma unroll
                     for (int i = 1; i < 9; ++i) {
                         const int rsrc = r - CY[i];
                         if (rsrc < 0 || rsrc >= ny) continue;
-                        if (solid(k - CX[i], rsrc, 1 - CY[i], near_sq, gB))
+                        if (solid(mkb, k - CX[i], rsrc, 1 - CY[i], near_sq))
                             p[i][k] = own[OPP[i] * RING_ROW + RING_CELL0 + 4 * lane + k];
                     }
                 }
             }
             collide_row<MODEL, OPEN>(m, p, part1, near_sq, x0, r, sponge);
             const unsigned rowoff = (unsigned)r * (unsigned)nx;
-            unsigned smask = 0;  // bit k: cell x0 + k is solid
-            if (near_b)
+            unsigned smask = (mkb >> 7) & 0xFu;  // bit k: cell x0 + k is solid
+            if (!OPEN && near_b)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) smask |= (solid(k, r, 1, near_sq, gB) ? 1u : 0u) << k;
+                for (int k = 0; k < 4; ++k) smask |= (solid(0u, k, r, 1, near_sq) ? 1u : 0u) << k;
             if (smask == 0) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
