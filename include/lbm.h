@@ -86,7 +86,9 @@ typedef struct {
 size_t lbm_state_floats(const lbm_member_desc* members, int32_t n_members);
 
 /*
- * Create a context for n_members trajectories.
+ * Create a context for n_members independent trajectories of the channel
+ * flow (paper Section 2: the flow past the square; Section 4: the rare-event
+ * algorithms work on an ensemble of such trajectories, run in parallel).
  *   pop_a, pop_b   caller-owned device buffers of pop_floats floats each
  *                  (>= lbm_state_floats), 16-byte aligned; states ping-pong
  *                  between them.
@@ -134,7 +136,10 @@ int lbm_set_active(lbm_ctx* ctx, const int32_t* active_host);
 
 /*
  * Advance every active member by n_steps steps (paper Appendix A: stream,
- * then collide), recording each step's drag in the member's next column and
+ * then collide).  The collision update is computed in FP64 from the FP32
+ * stored deviations and rounded once to FP32 on store (the drag of a step is
+ * summed in FP64 and stored in FP32).  Records each step's drag in the
+ * member's next column and
  * adding (f_d - mu)/sigma * dt to accum.  A member whose drag becomes
  * non-finite is flagged (lbm_flags).  LBM_ERANGE if an active member would
  * pass series_capacity.  Steps are grouped in chunks of 64 (one drag
@@ -150,7 +155,11 @@ int lbm_step_batch(lbm_ctx* ctx, int32_t n_steps);
    every kernel of every chunk (on = 0).  Both give bit-identical results. */
 int lbm_set_graphs(lbm_ctx* ctx, int32_t on);
 
-/* Copy drag columns [t0, t1) of every member into out_dev (device float[n][t1-t0]). */
+/* The drag on the square (paper Section 2.1: the x-force the flow exerts on
+   the obstacle; here by momentum exchange, see the conventions above) of steps
+   t0 .. t1-1 of every member: copies drag columns [t0, t1) into out_dev
+   (device float[n][t1-t0], row m = member m), enqueued on the context's
+   stream.  LBM_EINVAL unless 0 <= t0 <= t1 <= series_capacity. */
 int lbm_drag(const lbm_ctx* ctx, int32_t t0, int32_t t1, float* out_dev);
 
 /* Device pointer to member m's current state ([9][ny][nx] deviations). */
@@ -402,14 +411,22 @@ int tail_probability(const double* fmax_dev, const double* log_weight_dev, int32
 
 /*
  * AMS score built from a learned prediction ghat for the target event
- * {max_t F_T(t) >= level} (F_T: time-averaged drag): out = level where
- * ft >= level, else min(ghat, the float just below level) (-inf for a
- * non-finite ghat).  Then max_t out >= level exactly when the event happened,
- * which keeps the AMS estimate of its probability unbiased whatever the
- * prediction.  All arrays device float[count]; level finite and non-zero.
+ * {max_t F_T(t) >= level} (F_T: time-averaged drag; paper Section 4.1: the
+ * score may be any function of the state that reaches the level exactly when
+ * the event happens).  out = level where ft >= level; elsewhere the
+ * prediction mapped strictly increasingly into (-inf, level):
+ *   out = level - width * ln(1 + exp((level - ghat) / width)),
+ * computed in FP64, rounded to FP32 and held at or below the float just under
+ * the level; -inf for a non-finite ghat.  The map follows ghat far below the
+ * level (within width * exp(-(level - ghat)/width)) and approaches the level
+ * from below as ghat grows past it, so predictions above the level keep
+ * their order (FP32 resolves them until ghat exceeds the level by about
+ * width * ln(width / ulp(level))) instead of tying, and max_t out >= level
+ * exactly when the event happened.  All arrays device float[count]; level
+ * finite, width finite and > 0.
  */
-int ams_clamped_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level, float* out_dev,
-                      void* hip_stream);
+int ams_learned_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level, float width,
+                      float* out_dev, void* hip_stream);
 
 /*
  * Learned AMS score (the paper's conclusion proposes learning the score
@@ -445,9 +462,11 @@ int score_net_forward(const float* params_dev, const float* x_dev, int32_t batch
 /*
  * Gradient of the mean squared error (1/B) sum_b (y_b - label_b)^2 with
  * respect to every parameter (device float[score_net_params()]), and the loss
- * into loss_dev (device float, may be NULL).  Deterministic: per-image
- * contributions are added in image order within chunks of 64 images and the
- * chunk sums in chunk order; the loss by a fixed-order tree.
+ * into loss_dev (device float, may be NULL).  Deterministic for a given batch
+ * size: per-image contributions are added in image order within chunks of c
+ * images, c the smallest power of two from 8 to 256 with c * c >= batch (16
+ * at a batch of 256), then the chunk sums in chunk order; the loss by a
+ * fixed-order tree.
  */
 int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
                    float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes, void* hip_stream);

@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
-from typing import Callable, List
+from typing import Callable, List, Optional
 
 import numpy as np
 
@@ -81,6 +81,36 @@ def kill_branch(series: np.ndarray, n_kill: int, key: int, iteration: int) -> Ki
     return KillBranch(level, killed, parents, branch_t, False)
 
 
+def learned_score(ghat: np.ndarray, event: np.ndarray, level: float, width: float) -> np.ndarray:
+    """AMS score built on a learned prediction ghat of the target observable, for the event
+    {max_t event(t) >= level} (the score may be any function of the state as long as it reaches
+    the level exactly when the event happens, which keeps the estimate unbiased, Section 4.1).
+
+    Where event(t) >= level the score is the level.  Elsewhere it is a smooth, strictly
+    increasing map of the prediction into (-inf, level):
+        level - width * ln(1 + exp((level - ghat) / width)),
+    which follows ghat far below the level and approaches the level from below as ghat grows past
+    it, so over-predictions keep their order instead of all landing on one value.  A non-finite
+    prediction gives -inf.  FP64, element by element; `level` and `width` > 0 as given.
+    """
+    g = np.asarray(ghat, dtype=np.float64).ravel()
+    e = np.asarray(event, dtype=np.float64).ravel()
+    out = np.empty(g.shape)
+    for i in range(g.size):
+        if e[i] >= level:
+            out[i] = level
+        elif not math.isfinite(g[i]):
+            out[i] = -math.inf
+        else:
+            x = (level - g[i]) / width
+            # the same quantity written so that exp never overflows
+            if x > 0.0:
+                out[i] = g[i] - width * math.log1p(math.exp(-x))
+            else:
+                out[i] = level - width * math.log1p(math.exp(x))
+    return out.reshape(np.shape(ghat))
+
+
 def estimate(k_history: List[int], n: int, final_maxima: np.ndarray, levels: np.ndarray) -> np.ndarray:
     """Unbiased AMS estimate of P(max >= a) for each level a."""
     factor = 1.0
@@ -100,22 +130,24 @@ def return_time(prob: np.ndarray, t_a: float) -> np.ndarray:
 
 
 def run(init_paths: np.ndarray, resimulate: Callable, n_kill: int, key: int,
-        max_iter: int, threshold: float):
+        max_iter: int, threshold: float, score: Optional[Callable] = None):
     """Generic AMS loop for a toy dynamics given by whole paths.
 
-    init_paths: [N, T] score paths (the score is the state itself for OU).
-    resimulate(parent_path, t_b, slot, iteration) -> new path equal to the
-    parent on [0, t_b] and freshly simulated after.  Returns
-    dict(paths, k_history, levels, extinct).
+    init_paths: [N, T] state paths.  score(paths) -> [N, T] score series
+    (default: the state itself, as for OU).  resimulate(parent_path, t_b, slot,
+    iteration) -> new path equal to the parent on [0, t_b] and freshly
+    simulated after.  Returns dict(paths, scores, k_history, levels, extinct).
     """
+    score = (lambda p: p) if score is None else score
     paths = np.array(init_paths, dtype=np.float64)
     n = paths.shape[0]
     k_hist, levels = [], []
     extinct = False
     for it in range(max_iter):
-        if clean_maxima(paths).min() >= threshold:
+        xi = score(paths)
+        if clean_maxima(xi).min() >= threshold:
             break
-        kb = kill_branch(paths, n_kill, key, it)
+        kb = kill_branch(xi, n_kill, key, it)
         if kb.extinct:
             extinct = True
             break
@@ -125,4 +157,4 @@ def run(init_paths: np.ndarray, resimulate: Callable, n_kill: int, key: int,
         for slot, parent, tb in zip(kb.killed, kb.parents, kb.branch_t):
             new_paths[slot] = resimulate(paths[parent], int(tb), int(slot), it)
         paths = new_paths
-    return dict(paths=paths, k_history=k_hist, levels=levels, extinct=extinct)
+    return dict(paths=paths, scores=score(paths), k_history=k_hist, levels=levels, extinct=extinct)

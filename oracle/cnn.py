@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import Dict
+from typing import Callable, Dict, Optional
 
 import numpy as np
 
@@ -68,17 +68,26 @@ def conv3x3_weight_grad(gz: np.ndarray, x: np.ndarray) -> np.ndarray:
     return gw
 
 
-def forward(p: Dict[str, np.ndarray], x: np.ndarray):
-    """Returns (y [B], cache) for inputs x [B, C, 16, 16]."""
-    z1 = conv3x3(x, p["w1"], p["b1"])
-    a1 = np.maximum(z1, 0.0)
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, layer_input: Optional[Callable] = None):
+    """Returns (y [B], cache) for inputs x [B, C, 16, 16].
+
+    layer_input, if given, is applied to the input of each convolution (x, and
+    the activations of the first two layers) before it is convolved: a network
+    whose matrix products take their inputs in a narrower format (BF16) is this
+    one with the rounding to that format as layer_input.  The cache holds the
+    layer inputs as convolved, so the backward pass takes the rounding's
+    derivative as 1 (the weight gradients use the inputs the products saw)."""
+    li = (lambda a: a) if layer_input is None else layer_input
+    x_in = li(x)
+    z1 = conv3x3(x_in, p["w1"], p["b1"])
+    a1 = li(np.maximum(z1, 0.0))
     z2 = conv3x3(a1, p["w2"], p["b2"])
-    a2 = np.maximum(z2, 0.0)
+    a2 = li(np.maximum(z2, 0.0))
     z3 = conv3x3(a2, p["w3"], p["b3"])
     a3 = np.maximum(z3, 0.0)
     g = a3.mean(axis=(2, 3))
     y = g @ p["w4"] + p["b4"]
-    return y, dict(x=x, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, a3=a3, g=g)
+    return y, dict(x=x_in, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, a3=a3, g=g)
 
 
 def loss(y: np.ndarray, label: np.ndarray) -> float:

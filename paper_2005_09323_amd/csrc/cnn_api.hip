@@ -10,12 +10,12 @@
 using namespace lbm;
 
 namespace {
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct WsLayout {
     size_t wt, act, gap, y, partial, total;
 };
-WsLayout layout(int batch) {
-    WsLayout w;
+constexpr WsLayout layout(int batch) {
+    WsLayout w{};
     size_t off = 0;
     w.wt = off;
     off += align256((size_t)CNN_WT_ELEMS * sizeof(unsigned short));
@@ -30,6 +30,7 @@ WsLayout layout(int batch) {
     w.total = off;
     return w;
 }
+
 int check_ws(int batch, void* ws, size_t bytes) {
     if (batch < 1 || batch > (1 << 20)) return lbm_fail(LBM_EINVAL, "batch must be in [1, 2^20]");
     if (!ws) return lbm_fail(LBM_EINVAL, "NULL workspace");
@@ -90,14 +91,12 @@ extern "C" int score_net_forward(const float* params_dev, const float* x_dev, in
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "score forward");
 }
 
-extern "C" int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
-                              float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes,
-                              void* hip_stream) {
-    if (!params_dev || !x_dev || !labels_dev || !grads_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
-    int rc = check_ws(batch, workspace, workspace_bytes);
-    if (rc) return rc;
+namespace {
+// Forward (activations and averages saved) and backward of one batch into the
+// workspace at `base` laid out by layout(batch); enqueued on the stream.
+int grad_into(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch, float* grads_dev,
+              float* loss_dev, char* base, hipStream_t st) {
     const WsLayout w = layout(batch);
-    char* base = (char*)workspace;
     CnnArgs a{};
     a.params = params_dev;
     a.x = x_dev;
@@ -110,11 +109,21 @@ extern "C" int score_net_grad(const float* params_dev, const float* x_dev, const
     a.grads = grads_dev;
     a.loss = loss_dev;
     a.wt = (unsigned short*)(base + w.wt);
-    hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = launch_cnn_forward(a, st);
     if (e != hipSuccess) return lbm_hip_fail(e, "score forward");
     if ((e = launch_cnn_backward(a, st)) != hipSuccess) return lbm_hip_fail(e, "score backward");
     return LBM_OK;
+}
+}  // namespace
+
+extern "C" int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
+                              float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes,
+                              void* hip_stream) {
+    if (!params_dev || !x_dev || !labels_dev || !grads_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    int rc = check_ws(batch, workspace, workspace_bytes);
+    if (rc) return rc;
+    return grad_into(params_dev, x_dev, labels_dev, batch, grads_dev, loss_dev, (char*)workspace,
+                     (hipStream_t)hip_stream);
 }
 
 extern "C" int score_net_adam(float* params_dev, float* m_dev, float* v_dev, const float* grads_dev, int32_t step,

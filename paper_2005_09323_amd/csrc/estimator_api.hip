@@ -66,12 +66,13 @@ extern "C" int tail_probability(const double* fmax_dev, const double* log_weight
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "tail probability");
 }
 
-extern "C" int ams_clamped_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level,
-                                 float* out_dev, void* hip_stream) {
+extern "C" int ams_learned_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level,
+                                 float width, float* out_dev, void* hip_stream) {
     if (!ghat_dev || !ft_dev || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
     if (count < 0) return lbm_fail(LBM_EINVAL, "negative count");
-    if (!std::isfinite(level) || level == 0.0f) return lbm_fail(LBM_EINVAL, "level must be finite and non-zero");
+    if (!std::isfinite(level)) return lbm_fail(LBM_EINVAL, "level must be finite");
+    if (!(width > 0.0f) || !std::isfinite(width)) return lbm_fail(LBM_EINVAL, "width must be finite and > 0");
     if (count == 0) return LBM_OK;
-    hipError_t e = launch_clamped_score(ghat_dev, ft_dev, count, level, out_dev, (hipStream_t)hip_stream);
-    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "clamped score");
+    hipError_t e = launch_learned_score(ghat_dev, ft_dev, count, level, width, out_dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "learned score");
 }

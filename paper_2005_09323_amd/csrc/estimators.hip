@@ -78,21 +78,34 @@ __global__ void tail_probability_kernel(TailArgs a) {
 }
 
 // AMS score from a learned predictor, kept consistent with the target event
-// {max_t F_T(t) >= a}: the score is a once the time-averaged drag has reached
-// a, and the prediction held strictly below a before that, so that
-// max_t score >= a exactly when the event happened.
-__global__ void clamped_score_kernel(const float* ghat, const float* ft, long long count, float a, float* out) {
+// {max_t F_T(t) >= a}: the score is a once the time-averaged drag has reached a;
+// before that the prediction g is mapped strictly increasingly into (-inf, a),
+// a - w ln(1 + exp((a - g)/w)), so that max_t score >= a exactly when the event
+// happened while over-predictions keep their order.  Evaluated in FP64 in the
+// form whose exponential cannot overflow, rounded to FP32 (a monotone rounding)
+// and held at or below the float just under a.
+__global__ void learned_score_kernel(const float* ghat, const float* ft, long long count, float a, float w,
+                                     float* out) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const float below = __int_as_float(__float_as_int(a) - (a > 0.0f ? 1 : -1));  // next float under a
     const float g = ghat[i];
-    out[i] = ft[i] >= a ? a : (isfinite(g) ? fminf(g, below) : -INFINITY);
+    float s;
+    if (ft[i] >= a) {
+        s = a;
+    } else if (!isfinite(g)) {
+        s = -INFINITY;
+    } else {
+        const double x = ((double)a - (double)g) / (double)w;
+        const double v = x > 0.0 ? (double)g - (double)w * log1p(exp(-x)) : (double)a - (double)w * log1p(exp(x));
+        s = fminf((float)v, nextafterf(a, -INFINITY));
+    }
+    out[i] = s;
 }
 
-hipError_t launch_clamped_score(const float* ghat, const float* ft, long long count, float a, float* out,
+hipError_t launch_learned_score(const float* ghat, const float* ft, long long count, float a, float w, float* out,
                                 hipStream_t st) {
-    hipLaunchKernelGGL(clamped_score_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, ghat, ft,
-                       count, a, out);
+    hipLaunchKernelGGL(learned_score_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, ghat, ft,
+                       count, a, w, out);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ struct TailArgs {
     double* prob;
 };
 
-hipError_t launch_clamped_score(const float* ghat, const float* ft, long long count, float a, float* out,
+hipError_t launch_learned_score(const float* ghat, const float* ft, long long count, float a, float w, float* out,
                                 hipStream_t st);
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st);
 hipError_t launch_window_max(const WindowMaxArgs& a, int rows, hipStream_t st);

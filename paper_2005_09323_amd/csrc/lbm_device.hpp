@@ -32,7 +32,13 @@ namespace lbm {
 // links: bit i set when x + c_i lies in the square; returns the momentum
 // those links hand to the square, sum of 2 c_ix f_i^out (the w_i parts
 // cancel over the closed square, so deviations give the same total).
+//
+// Contraction is pinned per source expression (fp contract on: a * b + c
+// written in one expression may become one FMA, nothing across statements),
+// so that every kernel that inlines this function computes the same bits
+// whatever the optimizer does around it.
 __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsigned links) {
+#pragma clang fp contract(on)
     const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
     const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
     const double drho = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;
@@ -54,6 +60,7 @@ __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsign
     d[0] = (float)(keep * d0 + WD[0] * b);
     // pair (ip, im) with c_ip = -c_im; e = c_ip.J, v = c_ip.u; xmove: c_ip,x = +1 (else 0)
     auto pair = [&](int ip, int im, double dp, double dm, double e, double v, bool xmove) {
+#pragma clang fp contract(on)
         const double even = xmove ? fma(c45 * e, v, fma(m.gf9, v, b)) : fma(c45 * e, v, b);
         const double odd = xmove ? fma(c3, e, m.gf3) : c3 * e;
         const double op = fma(keep, dp, WD[ip] * (even + odd));
@@ -88,8 +95,10 @@ __device__ __forceinline__ double bgk_guo(const MemberDev& m, float d[9], unsign
 //   s4 for k22 (the conserved k00, k10, k01 end at rho, F/2, 0);
 //   the increments k* - k go back to raw moments by the inverse shift and to
 //   population increments by the inverse of the D2Q9 raw-moment matrix.
-// With every rate equal to omega this is the BGK + Guo update.
+// With every rate equal to omega this is the BGK + Guo update.  Contraction
+// is pinned per source expression, as in bgk_guo.
 __device__ __forceinline__ double cm_guo(const MemberDev& m, float d[9], unsigned links) {
+#pragma clang fp contract(on)
     const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
     const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
     const double dr = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;  // rho - 1

@@ -341,7 +341,8 @@ def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: i
             _states_to(src, ens)
             runner = rare.AmsRunner(ens, t_a, window, stride=32, ckpt_every=512, key=3000 + rep, eps=eps,
                                     snapshots=snaps, net=use_net, feature_args=fargs if use_net else None,
-                                    target=level if use_net else None)
+                                    target=level if use_net else None,
+                                    width=st.sigma_window[window] if use_net else None)
             t0 = _sync_time()
             res = runner.run(n_kill=max(1, int(n * n_kill_frac)), max_iter=max_iter, threshold=level)
             walls.append(_sync_time() - t0)

@@ -173,8 +173,9 @@ class AmsRunner:
 
     Every member runs t_a steps from its current state.  The score lives on a
     grid of `stride` steps: the time-averaged drag F_T(t) over the last `window`
-    steps (plain) or, with a score network, the network's prediction clamped
-    for the target level (learned).  A killed member restarts from its parent's
+    steps (plain) or, with a score network, the network's prediction mapped
+    strictly increasingly below the target level until the event has happened
+    (learned; `width` sets how soon the map bends towards the level).  A killed member restarts from its parent's
     last checkpoint before the branching time, replays the parent's dynamics
     exactly (the kernels are deterministic) up to the branching time, is
     perturbed there (Appendix D) and runs on to t_a.
@@ -182,11 +183,11 @@ class AmsRunner:
 
     def __init__(self, ens: Ensemble, t_a: int, window: int, stride: int, ckpt_every: int, key: int,
                  eps: float, snapshots: torch.Tensor, net=None, feature_args: Optional[dict] = None,
-                 target: Optional[float] = None):
+                 target: Optional[float] = None, width: Optional[float] = None):
         if t_a % ckpt_every or ckpt_every % stride:
             raise ValueError("t_a must be a multiple of ckpt_every, itself a multiple of stride")
-        if net is not None and (feature_args is None or target is None):
-            raise ValueError("a learned score needs feature_args and the target level")
+        if net is not None and (feature_args is None or target is None or width is None):
+            raise ValueError("a learned score needs feature_args, the target level and the map's width")
         if ens.capacity < t_a + 1:
             raise ValueError("the drag series needs t_a + 1 columns")
         self.ens, self.t_a, self.window, self.stride, self.ckpt = ens, t_a, window, stride, ckpt_every
@@ -195,6 +196,7 @@ class AmsRunner:
         # trajectory whose score reached the level also compares as having reached it here
         self.net, self.fargs = net, feature_args
         self.target = None if target is None else float(np.float32(target))
+        self.width = None if width is None else float(width)
         m = ens.members[0]
         self.state_floats = 9 * m.nx * m.ny
         n = ens.n
@@ -249,8 +251,8 @@ class AmsRunner:
         if self.net is None:
             return ft
         out = torch.empty_like(ft)
-        native.check(native.lib().ams_clamped_score(_ptr(self.ghat), _ptr(ft), ft.numel(), float(self.target),
-                                                    _ptr(out), _stream_handle(None)))
+        native.check(native.lib().ams_learned_score(_ptr(self.ghat), _ptr(ft), ft.numel(), float(self.target),
+                                                    self.width, _ptr(out), _stream_handle(None)))
         return out
 
     # -- the algorithm --------------------------------------------------------

@@ -211,11 +211,13 @@ static void check_free_functions() {
     CHECK(tail_probability(nullptr, cd, 4, cd, 2, d, nullptr) == LBM_EINVAL);
     CHECK(tail_probability(cd, cd, 0, cd, 2, d, nullptr) == LBM_EINVAL);
     CHECK(tail_probability(cd, cd, 4, cd, 0, d, nullptr) == LBM_EINVAL);
-    CHECK(ams_clamped_score(cf, cf, -1, 1.0f, f, nullptr) == LBM_EINVAL);
-    CHECK(ams_clamped_score(cf, cf, 4, 0.0f, f, nullptr) == LBM_EINVAL);
-    CHECK(ams_clamped_score(cf, cf, 4, NAN, f, nullptr) == LBM_EINVAL);
-    CHECK(ams_clamped_score(cf, cf, 0, 1.0f, f, nullptr) == LBM_OK);
-    CHECK(ams_clamped_score(nullptr, cf, 4, 1.0f, f, nullptr) == LBM_EINVAL);
+    CHECK(ams_learned_score(cf, cf, -1, 1.0f, 0.1f, f, nullptr) == LBM_EINVAL);
+    CHECK(ams_learned_score(cf, cf, 4, NAN, 0.1f, f, nullptr) == LBM_EINVAL);
+    CHECK(ams_learned_score(cf, cf, 4, 1.0f, 0.0f, f, nullptr) == LBM_EINVAL);
+    CHECK(ams_learned_score(cf, cf, 4, 1.0f, -1.0f, f, nullptr) == LBM_EINVAL);
+    CHECK(ams_learned_score(cf, cf, 4, 1.0f, INFINITY, f, nullptr) == LBM_EINVAL);
+    CHECK(ams_learned_score(cf, cf, 0, 0.0f, 0.1f, f, nullptr) == LBM_OK);
+    CHECK(ams_learned_score(nullptr, cf, 4, 1.0f, 0.1f, f, nullptr) == LBM_EINVAL);
     // score network
     const int32_t np = score_net_params();
     CHECK(np > 0);

@@ -398,3 +398,56 @@ def test_ams_on_lbm_matches_oracle_ams():
     gpu_drag = ens.series[:, 1:t_a + 1].double().cpu().numpy()
     ref_drag = np.array(drags)
     assert np.abs(gpu_drag - ref_drag).max() <= 1e-4 * np.abs(ref_drag).max()
+
+
+@pytest.mark.parametrize("level,width", [(0.0, 0.25), (1.7, 0.05), (-3.0, 1.0)])
+def test_learned_score_matches_oracle_and_keeps_order(level, width):
+    """ams_learned_score against the oracle's map: within one FP32 ulp of the FP64 value rounded to
+    FP32, exactly the level where the event observable reached it (and nowhere else), -inf for
+    non-finite predictions, never at or above the level otherwise, and predictions that
+    over-shoot the level keep their order (the hard clamp tied them all)."""
+    from paper_2005_09323_amd import native
+    from paper_2005_09323_amd.ensemble import _ptr, _stream_handle
+    rng = np.random.default_rng(11)
+    n = 40_000
+    ghat = (level + width * rng.uniform(-30.0, 12.0, n)).astype(np.float32)
+    ghat[:5] = [np.nan, np.inf, -np.inf, level, np.float32(level) + 10 * width]
+    ft = (level + width * rng.uniform(-5.0, 1.0, n)).astype(np.float32)
+    ft[:5] = level - 1.0
+    ft[5] = level                               # the event reached exactly at the level
+    g, f = torch.from_numpy(ghat).cuda(), torch.from_numpy(ft).cuda()
+    out = torch.empty_like(g)
+    native.check(native.lib().ams_learned_score(_ptr(g), _ptr(f), n, level, width, _ptr(out),
+                                                _stream_handle(None)))
+    got = out.cpu().numpy()
+    ref = oams.learned_score(ghat.astype(np.float64), ft.astype(np.float64), float(np.float32(level)),
+                             float(np.float32(width)))
+    lev32 = np.float32(level)
+    hit = ft >= lev32
+    assert np.array_equal(got == lev32, hit)
+    assert np.all(got[~hit] < lev32)
+    assert got[0] == -np.inf and got[1] == -np.inf and got[2] == -np.inf
+    fin = np.isfinite(ref) & ~hit
+    ref32 = np.minimum(ref[fin].astype(np.float32), np.nextafter(lev32, np.float32(-np.inf)))
+    ulp = np.spacing(np.abs(ref32)).astype(np.float64)
+    assert np.all(np.abs(got[fin].astype(np.float64) - ref32.astype(np.float64)) <= ulp), \
+        np.max(np.abs(got[fin].astype(np.float64) - ref32) / ulp)
+    # order: monotone everywhere, and strictly increasing on a grid from the level up to 8 widths
+    # above it (FP32 resolves the approach that far)
+    order = np.argsort(ghat[fin], kind="stable")
+    assert np.all(np.diff(got[fin][order]) >= 0)
+    grid = (lev32 + np.float32(width) * np.arange(0, 8.01, 0.5, dtype=np.float32)).astype(np.float32)
+    gg, ff = torch.from_numpy(grid).cuda(), torch.full((grid.size,), -np.inf, device="cuda")
+    og = torch.empty_like(gg)
+    native.check(native.lib().ams_learned_score(_ptr(gg), _ptr(ff), grid.size, level, width, _ptr(og),
+                                                _stream_handle(None)))
+    assert np.all(np.diff(og.cpu().numpy()) > 0)
+
+
+def test_learned_score_argument_errors():
+    from paper_2005_09323_amd import native
+    from paper_2005_09323_amd.ensemble import _ptr, _stream_handle
+    g = torch.zeros(4, device="cuda")
+    for level, width in ((float("nan"), 1.0), (1.0, 0.0), (1.0, -1.0), (1.0, float("inf"))):
+        rc = native.lib().ams_learned_score(_ptr(g), _ptr(g), 4, level, width, _ptr(g), _stream_handle(None))
+        assert rc == native.LBM_EINVAL

@@ -1,12 +1,24 @@
 """GPU parity of the learned score: features, network forward/backward on BF16
 matrix cores, Adam.
 
-The oracle runs in FP64 on the same BF16-rounded weights and inputs; the GPU
-also rounds each hidden layer's activations (and gradients) to BF16 before
-the next matrix-core product, so network outputs and gradients are compared
-by relative L2 norm per tensor: <= 1e-2 (outputs) and <= 3e-2 (gradients),
-a few BF16 roundings (2^-8 each) deep.  Features and Adam are FP32/FP64
-elementwise: <= 1e-6 relative.
+The network is defined with BF16 products: weights and the input of every
+convolution are rounded to BF16 (nearest even), sums are FP32.  Two oracle
+references, both FP64 on the same BF16-rounded weights and pictures:
+* the network as defined: the oracle's forward with the input of each
+  convolution rounded to BF16 too.  Outputs then differ only by FP32
+  accumulation (relative L2 <= 1e-4; an FP32 emulation gives 6e-6 at batch
+  256) and gradients only by the kernel's BF16 rounding of the back-propagated
+  signals dZ before its matrix products (<= 5e-3 per tensor; the emulation
+  gives 1.5e-3 at batch 16, 4.4e-4 at 256);
+* the FP64 network without that rounding of hidden activations: outputs
+  <= 1e-2, gradients <= 3e-2 per tensor.  The loose gradient bound is
+  measured: ReLU masks flip where a hidden value is within a BF16 rounding of
+  zero, which moves the first layer's weight gradient by 2.0e-2 at batch 16
+  (w1; every other tensor <= 5.5e-3), and an emulation of the BF16 rounding
+  alone reproduces those figures to two digits.
+Batch 256 is the training batch of the product, whose gradient sum runs in
+16 chunks of 16 images.  Features and Adam are FP32/FP64 elementwise: <= 1e-6
+relative.
 """
 import numpy as np
 import pytest
@@ -58,32 +70,46 @@ def _rel_l2(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-@pytest.mark.parametrize("batch", [1, 7, 64])
+@pytest.mark.parametrize("batch", [1, 7, 64, 256])
 def test_forward_matches_oracle(batch):
     p = workloads.cnn_params(11)
     x, _ = workloads.cnn_batch(batch, 12)
     net = _net(_flat(p), batch)
     y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
+    ref_bf16, _ = ocnn.forward(_bf16_params(p), _bf16(x.astype(np.float32)), layer_input=_bf16)
     ref, _ = ocnn.forward(_bf16_params(p), _bf16(x.astype(np.float32)))
+    print(f"batch {batch} forward relative L2: {_rel_l2(y, ref_bf16):.2e} (BF16 layer inputs), "
+          f"{_rel_l2(y, ref):.2e} (FP64 hidden activations)")
+    assert _rel_l2(y, ref_bf16) <= 1e-4, _rel_l2(y, ref_bf16)
     assert _rel_l2(y, ref) <= 1e-2, _rel_l2(y, ref)
 
 
-def test_gradients_match_oracle():
+@pytest.mark.parametrize("batch", [16, 256])
+def test_gradients_match_oracle(batch):
     p = workloads.cnn_params(21)
-    x, lab = workloads.cnn_batch(16, 22)
-    net = _net(_flat(p), 16)
+    x, lab = workloads.cnn_batch(batch, 22)
+    net = _net(_flat(p), batch)
     xt = torch.from_numpy(x.astype(np.float32)).cuda()
     lt = torch.from_numpy(lab.astype(np.float32)).cuda()
     g = net.grad(xt, lt).cpu().numpy().astype(np.float64)
     qp = _bf16_params(p)
     xb = _bf16(x.astype(np.float32))
-    y, cache = ocnn.forward(qp, xb)
-    ref = ocnn.backward(qp, cache, y, lab.astype(np.float32).astype(np.float64))
+    lab64 = lab.astype(np.float32).astype(np.float64)
     gg = _unflat(g)
+    yb, cb = ocnn.forward(qp, xb, layer_input=_bf16)
+    ref_bf16 = ocnn.backward(qp, cb, yb, lab64)
+    y, cache = ocnn.forward(qp, xb)
+    ref = ocnn.backward(qp, cache, y, lab64)
+    errs_bf16 = {k: _rel_l2(gg[k], ref_bf16[k]) for k in NAMES}
+    errs = {k: _rel_l2(gg[k], ref[k]) for k in NAMES}
+    print(f"batch {batch} gradient relative L2 per tensor, BF16 layer inputs:",
+          {k: f"{v:.2e}" for k, v in errs_bf16.items()})
+    print(f"batch {batch} gradient relative L2 per tensor, FP64 hidden activations:",
+          {k: f"{v:.2e}" for k, v in errs.items()})
     for k in NAMES:
-        err = _rel_l2(gg[k], ref[k])
-        assert err <= 3e-2, (k, err)
-    loss_ref = ocnn.loss(y, lab.astype(np.float32).astype(np.float64))
+        assert errs_bf16[k] <= 5e-3, (k, errs_bf16[k])
+        assert errs[k] <= 3e-2, (k, errs[k])
+    loss_ref = ocnn.loss(y, lab64)
     assert abs(net.loss.item() / loss_ref - 1) < 1e-2
 
 

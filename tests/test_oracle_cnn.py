@@ -80,3 +80,21 @@ def test_adam_fits_a_tiny_regression():
             first = cnn.loss(y, lab)
         opt.step(p, cnn.backward(p, cache, y, lab))
     assert cnn.loss(cnn.forward(p, x)[0], lab) < 0.5 * first
+
+
+def test_layer_input_hook_touches_exactly_the_three_convolution_inputs():
+    """With zero biases the network is positively homogeneous layer by layer, so doubling the
+    input of each of the three convolutions (and nothing else) multiplies y - b4 by exactly 8;
+    the cache holds the doubled inputs.  The identity hook changes nothing."""
+    import workloads
+    p = {k: np.asarray(v, dtype=np.float64) for k, v in workloads.cnn_params(4).items()}
+    for k in ("b1", "b2", "b3"):
+        p[k] = np.zeros_like(p[k])
+    x, _ = workloads.cnn_batch(3, 5)
+    y0, c0 = cnn.forward(p, x)
+    y1, c1 = cnn.forward(p, x, layer_input=lambda a: a)
+    assert np.array_equal(y0, y1)
+    y2, c2 = cnn.forward(p, x, layer_input=lambda a: 2.0 * a)
+    assert np.allclose(y2 - p["b4"], 8.0 * (y0 - p["b4"]), rtol=1e-13, atol=0)
+    assert np.array_equal(c2["x"], 2.0 * x)
+    assert np.allclose(c2["a1"], 4.0 * c0["a1"], rtol=1e-14) and np.allclose(c2["a2"], 8.0 * c0["a2"], rtol=1e-14)
