@@ -471,6 +471,24 @@ int score_net_forward(const float* params_dev, const float* x_dev, int32_t batch
 int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
                    float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/*
+ * score_net_grad for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels, arguments and results as score_net_grad (bit for
+ * bit), but the workspace is a static array of the library (31 MiB, the
+ * workspace of a batch of 256 images) that every GPU the library runs on
+ * holds until the process ends; no call allocates or frees anything.
+ * batch in [1, 256], else LBM_EINVAL.  The first call on each device looks
+ * up that device's copy of the array (hipGetSymbolAddress; make it outside
+ * any graph capture); later calls only enqueue kernels on hip_stream, which
+ * must belong to the current device.  All calls on one device share its
+ * array: calls that overlap in time on one device race (serialise them, for
+ * instance on one stream).  Nothing in the array needs clearing: each call
+ * writes every part of it that it reads.
+ */
+int score_net_grad_noalloc(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
+                           float* grads_dev, float* loss_dev, void* hip_stream);
+
 /* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on FP32 parameters with moments m, v. */
 int score_net_adam(float* params_dev, float* m_dev, float* v_dev, const float* grads_dev, int32_t step,
                    double lr, double beta1, double beta2, double eps, void* hip_stream);

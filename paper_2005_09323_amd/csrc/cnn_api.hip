@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/lbm.h"
 #include "api_internal.hpp"
@@ -29,6 +30,40 @@ constexpr WsLayout layout(int batch) {
     off += align256((size_t)batch * CNN_N_PARAMS * sizeof(float));
     w.total = off;
     return w;
+}
+
+// Workspace of score_net_grad_noalloc: a file-scope device array with the
+// layout of a caller's workspace for the largest batch that entry point
+// accepts (each region of a smaller batch starts at the same or a lower
+// offset and is shorter, so it fits too).  Every device the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address is taken
+// once per device with hipGetSymbolAddress and only that address is used.
+constexpr int NOALLOC_MAX_BATCH = 256;
+constexpr size_t NOALLOC_BYTES = layout(NOALLOC_MAX_BATCH).total;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, resolved on the first
+// call per device (no allocation: the array is part of the loaded code object).
+int scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return lbm_hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return lbm_fail(LBM_EUNSUPPORTED, "device %d beyond %d devices", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return lbm_hip_fail(e, "hipGetSymbolAddress of the static workspace");
+        if (!p) return lbm_fail(LBM_EHIP, "hipGetSymbolAddress gave a NULL address for the static workspace");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
 }
 
 int check_ws(int batch, void* ws, size_t bytes) {
@@ -124,6 +159,18 @@ extern "C" int score_net_grad(const float* params_dev, const float* x_dev, const
     if (rc) return rc;
     return grad_into(params_dev, x_dev, labels_dev, batch, grads_dev, loss_dev, (char*)workspace,
                      (hipStream_t)hip_stream);
+}
+
+extern "C" int score_net_grad_noalloc(const float* params_dev, const float* x_dev, const float* labels_dev,
+                                      int32_t batch, float* grads_dev, float* loss_dev, void* hip_stream) {
+    if (!params_dev || !x_dev || !labels_dev || !grads_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (batch < 1 || batch > NOALLOC_MAX_BATCH)
+        return lbm_fail(LBM_EINVAL, "batch %d outside [1, %d]: the static workspace holds %d images (%zu bytes)",
+                        batch, NOALLOC_MAX_BATCH, NOALLOC_MAX_BATCH, NOALLOC_BYTES);
+    void* ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return grad_into(params_dev, x_dev, labels_dev, batch, grads_dev, loss_dev, (char*)ws, (hipStream_t)hip_stream);
 }
 
 extern "C" int score_net_adam(float* params_dev, float* m_dev, float* v_dev, const float* grads_dev, int32_t step,

@@ -79,6 +79,7 @@ _SIG = {
     "score_features": (ctypes.c_int, [_P, _I, _I, _I, _I, _I, _I, _D, _D, _P]),
     "score_net_forward": (ctypes.c_int, [_P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "score_net_grad": (ctypes.c_int, [_P, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
+    "score_net_grad_noalloc": (ctypes.c_int, [_P, _P, _P, _I, _P, _P, _P]),
     "score_net_adam": (ctypes.c_int, [_P, _P, _P, _P, _I, _D, _D, _D, _D, _P]),
     "gktl_rebuild": (ctypes.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _D, _P, _P, _P, _P]),
     "window_mean_max": (ctypes.c_int, [_P, _I, _I, _I, _P, _P, _P]),

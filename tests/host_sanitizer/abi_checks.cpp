@@ -242,6 +242,10 @@ static void check_free_functions() {
     CHECK(score_net_grad(cf, cf, cf, 256, f, f, ws, w256 - 256, nullptr) == LBM_EINVAL);
     CHECK(score_net_grad(cf, cf, nullptr, 256, f, f, ws, w256, nullptr) == LBM_EINVAL);
     CHECK(score_net_grad(cf, cf, cf, (1 << 20) + 1, f, f, ws, w256, nullptr) == LBM_EINVAL);
+    CHECK(score_net_grad_noalloc(cf, cf, cf, 0, f, f, nullptr) == LBM_EINVAL);
+    CHECK(score_net_grad_noalloc(cf, cf, cf, 257, f, f, nullptr) == LBM_EINVAL);
+    CHECK(score_net_grad_noalloc(nullptr, cf, cf, 16, f, f, nullptr) == LBM_EINVAL);
+    CHECK(score_net_grad_noalloc(cf, cf, cf, 16, nullptr, f, nullptr) == LBM_EINVAL);
     CHECK(score_net_adam(f, f, f, cf, 0, 1e-3, 0.9, 0.999, 1e-8, nullptr) == LBM_EINVAL);
     CHECK(score_net_adam(f, f, f, cf, 1, 0.0, 0.9, 0.999, 1e-8, nullptr) == LBM_EINVAL);
     CHECK(score_net_adam(f, f, f, cf, 1, 1e-3, 1.0, 0.999, 1e-8, nullptr) == LBM_EINVAL);
