@@ -20,9 +20,12 @@
  *   must keep one fluid cell to every side: 1 <= sq_x0, sq_x0 + s <= nx - 1,
  *   1 <= sq_y0, sq_y0 + s <= ny - 1.  s = 0 means no obstacle.
  * - Populations are stored as FP32 deviations d_i = f_i - w_i from the
- *   rest state, structure-of-arrays: member m occupies 9*nx*ny floats
- *   starting at the sum of 9*nx*ny over members 0..m-1, laid out
- *   [i][y][x] with x fastest.  What is stored for step t is the
+ *   rest state, structure-of-arrays: member m occupies a block of 9*nx*ny
+ *   floats, laid out [i][y][x] with x fastest, in one of the two buffers.
+ *   At lbm_create the block of member m starts at the sum of 9*nx*ny over
+ *   members 0..m-1; a GKTL cloning may hand blocks from member to member
+ *   (gktl_select_clone), so lbm_member_state and lbm_copy_state_in/out are
+ *   the way to a member's current state.  What is stored for step t is the
  *   post-collision state f_i^out(t); streaming happens when step t+1 reads
  *   it.  Solid cells (the square, an open channel's grid bars) are never
  *   written by the lattice steps, and what they hold never enters a result.
@@ -233,13 +236,17 @@ int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third
  *           shear rate;
  *   outlet  ghost column x = nx rebuilt before every step from the stored
  *           state (the post-collision populations f of the last step), per
- *           row: density 1, u_g = 2 u(nx-1) - u(nx-2) with u = sum c_i f_i /
- *           sum f_i, strain S from differences (d/dx the extrapolation
- *           slope, d/dy centred, one-sided in the first and last rows), and
- *           g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) :
- *           Pi, Pi = -2 c_s^2 (tau(nx-1) - 1) S.  (The paper extrapolates
- *           the density too; with an equilibrium inlet that leaves the
- *           pressure level free, so the outlet holds it at the inlet's.)
+ *           row: u_g = 2 u(nx-1) - u(nx-2) with u = sum c_i f_i / sum f_i,
+ *           density rho_g = 1 (outlet_density = 0) or rho_g = 2 rho(nx-1) -
+ *           rho(nx-2) (outlet_density = 1, the paper's second-order
+ *           extrapolation of the density), strain S from differences (d/dx
+ *           the extrapolation slope, d/dy centred, one-sided in the first
+ *           and last rows), and g_i = f_i^eq(rho_g, u_g) + w_i / (2 c_s^4)
+ *           (c_i c_i - c_s^2 I) : Pi, Pi = -2 rho_g c_s^2 (tau(nx-1) - 1) S.
+ *           With the unit-density inlet, an extrapolated outlet density
+ *           leaves the channel's pressure level and flow rate to the outlet
+ *           (small channels fill until the flow stops, drain to twice the
+ *           inlet's flux, or blow up, by tau), hence the default 0.
  * Requirements (every member): grid within columns 1 .. nx - 3 and, with a
  * square, ending at least two columns before it; the square at least two
  * columns from the inlet (sq_x0 >= 2) and three from the outlet
@@ -258,7 +265,7 @@ typedef struct {
     int32_t grid_x0;       /* first column of the grid bars */
     int32_t grid_bar;      /* bar height = width = gap; 0 = no grid */
     int32_t sponge_x0;     /* last column before the sponge ramp */
-    int32_t reserved;      /* must be 0 */
+    int32_t outlet_density; /* 0: held at 1 (default); 1: extrapolated to second order */
     double sponge_tau;     /* relaxation time at the outlet column, > 1/2 */
 } lbm_open_channel;
 
@@ -312,6 +319,13 @@ int lbm_autotune_cached(lbm_ctx* ctx, int32_t n_steps, const char* path, int32_t
  *   perturbed: f <- f + eps * sum_n alpha_n f^(n) with alpha_n from key
  *   (key, PRTB), counter (m, period, n / 4, 0), word n % 4, then scaled by
  *   one factor that restores its mass before perturbation.
+ *   How the copies are made (lbm_set_cloning): by default the exact copy of
+ *   ancestor n takes over n's block, so it moves no data, and each further
+ *   copy is written (copied or perturbed) into the block of a state that
+ *   left no descendant (the k-th further copy in slot order into the k-th
+ *   such block in slot order), so that only further copies cost memory
+ *   traffic; or every copy is gathered into the other buffer.  The states,
+ *   drag and results of every later call are the same bit for bit.
  *   snapshots: device, n_snap <= 16 states in this library's deviation
  *   layout ([n_snap][9][ny][nx]), 16-byte aligned; may be NULL when
  *   eps == 0 or n_snap == 0.
@@ -323,6 +337,12 @@ int lbm_autotune_cached(lbm_ctx* ctx, int32_t n_steps, const char* path, int32_t
 int gktl_select_clone(lbm_ctx* ctx, double k, uint64_t key, int32_t period,
                       double eps, const float* snapshots, int32_t n_snap,
                       int32_t* ancestors_dev, double* ln_r_dev);
+
+/* How gktl_select_clone makes its copies: relabel = 1 (the default) moves
+   only the copies beyond the first of each ancestor, relabel = 0 gathers
+   every copy into the other buffer (each member keeps its block).  Same
+   results either way. */
+int lbm_set_cloning(lbm_ctx* ctx, int32_t relabel);
 
 /*
  * Perturb selected members in place (paper Appendix D) without cloning:

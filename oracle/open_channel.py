@@ -20,13 +20,14 @@ here (and by the device code):
 * sponge: tau(x) = tau + (tau_s - tau) r^2, r = (x - xs)/(nx - 1 - xs), for
   x > xs (tau elsewhere);
 * outlet: a ghost column at x = nx holds the post-collision populations of
-  a virtual cell (what a cell at x = nx - 1 pulls), per row: density 1 and
+  a virtual cell (what a cell at x = nx - 1 pulls), per row: the velocity
   u_g = 2 u(nx-1) - u(nx-2) from the post-collision state (the momentum of a
-  post-collision cell is that of its step).  The paper extrapolates the
-  density too; with the equilibrium inlet that leaves the pressure level
-  free, and the channel fills up until the flow stops (zero-gradient and
-  copied outlets) or blows up (second-order density), so the outlet holds
-  it at the inlet's value;
+  post-collision cell is that of its step), and the density rho_g either
+  extrapolated the same way, rho_g = 2 rho(nx-1) - rho(nx-2), as the paper
+  says (outlet_rho = 1), or held at the inlet's value 1 (outlet_rho = 0, the
+  default: with an equilibrium inlet that fixes the velocity, an outlet that
+  extrapolates the density too leaves the pressure level of the channel
+  free, and it drifts; the oracle's tests measure that drift);
   the strain S from finite differences (d/dx: the extrapolation slope
   u(nx-1) - u(nx-2); d/dy: centred differences of u_g, one-sided in the
   first and last row), and f_i = f_i^eq(rho_g, u_g) + w_i / (2 c_s^4) Q_i : Pi
@@ -51,6 +52,7 @@ class OpenChannel:
     bar: int            # bar height = bar width = spacing
     sponge_x0: int      # last column before the sponge ramp (>= nx - 1: no sponge)
     sponge_tau: float   # relaxation time at the outlet column
+    outlet_rho: int = 0  # outlet density: 0 held at 1, 1 extrapolated to second order
 
 
 def grid_mask(ny: int, nx: int, oc: OpenChannel) -> np.ndarray:
@@ -98,8 +100,8 @@ def outlet_ghost(ch, fout: np.ndarray) -> np.ndarray:
         return rho, ux, uy
 
     r1, ux1, uy1 = moments(fout[:, :, ch.nx - 1])
-    _, ux2, uy2 = moments(fout[:, :, ch.nx - 2])
-    rho = np.ones_like(r1)
+    r2, ux2, uy2 = moments(fout[:, :, ch.nx - 2])
+    rho = 2 * r1 - r2 if ch.open.outlet_rho else np.ones_like(r1)
     ux = 2 * ux1 - ux2
     uy = 2 * uy1 - uy2
 

@@ -32,6 +32,12 @@ struct RareScratch {
     double* mass_partial = nullptr;
     int *mode = nullptr, *src = nullptr, *need_mass = nullptr, *flags_new = nullptr, *status = nullptr;
     int* status_host = nullptr;
+    // relabelling clone: new block and buffer of every slot, the slots written
+    long long* new_off = nullptr;
+    int *new_parity = nullptr, *extra = nullptr, *n_extra = nullptr;
+    // pinned read-back of the tables above (the host mirrors follow them)
+    long long* new_off_host = nullptr;
+    int *new_parity_host = nullptr, *n_extra_host = nullptr;
 };
 
 // What a captured chunk of lbm_step_batch depends on besides device memory:
@@ -96,6 +102,9 @@ struct lbm_ctx {
     int total_blocks2 = 0;
     lbm::Segment seg2[lbm::MAX_SEGMENTS];
     RareScratch rare;
+    // GKTL cloning by relabelling member blocks (1, the default) or by gathering
+    // every copy into the other buffer (0); both give the same states
+    int relabel = 1;
     // full chunks of lbm_step_batch replay one captured HIP graph (captured on
     // a private stream, launched on `stream`)
     bool graphs = true;

@@ -76,7 +76,7 @@ struct MemberDev {
     // open channel (zero otherwise)
     int gx0, bar;         // grid bars: columns gx0 .. gx0 + bar - 1 (bar = 0: no grid)
     int sp_x0;            // last column before the sponge ramp (>= nx - 1: no sponge)
-    int pad_;
+    int out_rho;          // outlet density: 0 held at 1, 1 extrapolated to second order
     double tau;           // relaxation time outside the sponge
     double tau_sp;        // relaxation time at the outlet column
     double sp_inv;        // 1 / (nx - 1 - sp_x0) (0: no sponge)

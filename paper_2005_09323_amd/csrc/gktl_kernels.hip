@@ -11,6 +11,8 @@
 
 namespace lbm {
 
+typedef float f4g __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double block_max(double v, double* sh) {
     const int t = (int)threadIdx.x, nt = (int)blockDim.x;
     sh[t] = v;
@@ -98,6 +100,54 @@ __global__ __launch_bounds__(1024) void gktl_select_kernel(SelectArgs a) {
     __syncthreads();
     for (int m = t; m < n; m += nt)
         if (a.mode[m] == MODE_PERTURB) a.need_mass[a.src[m]] = 1;
+    if (!a.relabel) return;
+    // Relabelling: the first copy of each ancestor keeps the ancestor's block
+    // and buffer; the k-th further copy (in slot order) takes the block of the
+    // k-th state (in slot order) that left no descendant.  There are as many
+    // such states as further copies, and no copy reads them.  Ranks by a
+    // block-wide exclusive prefix count over slot order (each thread counts
+    // PER consecutive slots, then a scan over the threads).
+    constexpr int PER = MAX_SELECT / 1024;
+    __shared__ int scan_dead[1024], scan_extra[1024];
+    __shared__ int dead_state[MAX_SELECT];
+    const int b0 = t * PER;
+    int cd = 0, ce = 0;
+    for (int j = 0; j < PER; ++j) {
+        const int m = b0 + j;
+        if (m < n) {
+            cd += first_slot[m] == 0x7fffffff ? 1 : 0;
+            ce += first_slot[a.ancestors[m]] != m ? 1 : 0;
+        }
+    }
+    scan_dead[t] = cd;
+    scan_extra[t] = ce;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+        const int vd = t >= off ? scan_dead[t - off] : 0, ve = t >= off ? scan_extra[t - off] : 0;
+        __syncthreads();
+        scan_dead[t] += vd;
+        scan_extra[t] += ve;
+        __syncthreads();
+    }
+    int rd = scan_dead[t] - cd, re = scan_extra[t] - ce;  // exclusive ranks of this thread's first slot
+    for (int j = 0; j < PER; ++j) {
+        const int m = b0 + j;
+        if (m < n && first_slot[m] == 0x7fffffff) dead_state[rd++] = m;
+    }
+    __syncthreads();
+    for (int j = 0; j < PER; ++j) {
+        const int m = b0 + j;
+        if (m >= n) break;
+        const int anc = a.ancestors[m];
+        a.new_parity[m] = a.parity[anc];
+        if (first_slot[anc] == m) {
+            a.new_off[m] = a.members[anc].off;
+        } else {
+            a.new_off[m] = a.members[dead_state[re]].off;
+            a.extra[re++] = m;
+        }
+    }
+    if (t == 1023) *a.n_extra = scan_extra[1023];
 }
 
 // Host-chosen modes (in-place perturbation of selected members): fill the
@@ -139,16 +189,28 @@ __global__ __launch_bounds__(256) void mass_partial_kernel(MassArgs a) {
     double acc = 0.0;
     if (b0 < total) {
         const long long e1 = min(b0 + MASS_CHUNK, total);
-        long long e = b0 + threadIdx.x;
-        // the cell of the first element by division, the next ones by stepping 256 cells on
-        const long long cell = e % plane;
-        int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
-        for (; e < e1; e += 256) {
-            if (!in_solid(m, x, y)) acc += (double)base[e];
-            x += 256;
-            while (x >= m.nx) {
-                x -= m.nx;
-                if (++y == m.ny) y = 0;
+        if ((m.nx & 3) == 0) {
+            // four cells of one row per thread and load (a row never splits a vector)
+            for (long long e = b0 + 4 * threadIdx.x; e < e1; e += 1024) {
+                const f4g v = *(const f4g*)(base + e);
+                const long long cell = e % plane;
+                const int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (!in_solid(m, x + k, y)) acc += (double)v[k];
+            }
+        } else {
+            long long e = b0 + threadIdx.x;
+            // the cell of the first element by division, the next ones by stepping 256 cells on
+            const long long cell = e % plane;
+            int y = (int)(cell / m.nx), x = (int)(cell - (long long)y * m.nx);
+            for (; e < e1; e += 256) {
+                if (!in_solid(m, x, y)) acc += (double)base[e];
+                x += 256;
+                while (x >= m.nx) {
+                    x -= m.nx;
+                    if (++y == m.ny) y = 0;
+                }
             }
         }
     }
@@ -190,7 +252,14 @@ __global__ void mass_scale_kernel(ScaleArgs a) {
 // blockIdx.y = member; each thread moves 4 consecutive floats with 16-byte
 // accesses when the member block allows it (a plane of a multiple-of-4
 // width never splits a vector between two directions).
-typedef float f4g __attribute__((ext_vector_type(4)));
+// The perturbation's arithmetic, shared by every kernel that writes a
+// perturbed copy (so that all of them give the same bits):
+//   ad += alpha_q d^(q) (snapshots in order q = 0, 1, ...), then
+//   d_new = s (d_src + eps ad) + c_w w_i, with explicit FMAs.
+__device__ __forceinline__ double perturb_acc(double ad, double al, float sv) { return fma(al, (double)sv, ad); }
+__device__ __forceinline__ float perturb_out(float v, double ad, double s, double eps, double cw) {
+    return (float)fma(s, fma(eps, ad, (double)v), cw);
+}
 
 __global__ __launch_bounds__(256) void clone_gather_kernel(GatherArgs a) {
     const int m = (int)blockIdx.y;
@@ -218,11 +287,11 @@ __global__ __launch_bounds__(256) void clone_gather_kernel(GatherArgs a) {
             const double al = a.alpha[(long long)m * MAX_SNAP + q];
             const f4g sv = *(const f4g*)(a.snapshots + (long long)q * total + e0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) ad[k] += al * (double)sv[k];
+            for (int k = 0; k < 4; ++k) ad[k] = perturb_acc(ad[k], al, sv[k]);
         }
         const double s = a.scale[m], cw = a.coef_w[m] * WD[i], eps = a.eps;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = (float)(s * ((double)v[k] + eps * ad[k]) + cw);
+        for (int k = 0; k < 4; ++k) acc[k] = perturb_out(v[k], ad[k], s, eps, cw);
         *(f4g*)(dp + e0) = acc;
         return;
     }
@@ -231,14 +300,14 @@ __global__ __launch_bounds__(256) void clone_gather_kernel(GatherArgs a) {
         for (int k = 0; k < cnt; ++k) dp[e0 + k] = sp[e0 + k];
         return;
     }
-    const double s = a.scale[m], cw = a.coef_w[m], eps = a.eps;
+    const double s = a.scale[m], eps = a.eps;
     for (int k = 0; k < cnt; ++k) {
         const long long e = e0 + k;
         const int i = (int)(e / plane);
-        double acc = 0.0;
+        double ad = 0.0;
         for (int q = 0; q < a.n_snap; ++q)
-            acc += a.alpha[(long long)m * MAX_SNAP + q] * (double)a.snapshots[(long long)q * total + e];
-        dp[e] = (float)(s * ((double)sp[e] + eps * acc) + cw * WD[i]);
+            ad = perturb_acc(ad, a.alpha[(long long)m * MAX_SNAP + q], a.snapshots[(long long)q * total + e]);
+        dp[e] = perturb_out(sp[e], ad, s, eps, a.coef_w[m] * WD[i]);
     }
 }
 
@@ -259,6 +328,115 @@ __global__ void clone_commit_kernel(FinishArgs a) {
     if (m >= a.n || a.mode[m] == MODE_SKIP) return;
     a.parity[m] ^= 1;
     if (a.reset_accum) a.flags[m] = a.flags_new[m];
+}
+
+// Relabelling clone: the further copies extra[PLACE_GROUP * blockIdx.y + g]
+// get their ancestor's state (copy) or its perturbation (the arithmetic of
+// clone_gather_kernel), written into their new blocks in the ancestor's
+// buffer.  A workgroup serves a group of copies over one stretch of cells, so
+// that each snapshot word is read once for the whole group.  Sources are
+// blocks of ancestors, destinations blocks of states without descendant:
+// never the same block.
+constexpr int PLACE_GROUP = 8;
+
+__global__ __launch_bounds__(256) void clone_place_kernel(PlaceArgs a) {
+    const int g0 = (int)blockIdx.y * PLACE_GROUP;
+    const int ng = min(PLACE_GROUP, a.n_extra - g0);
+    const MemberDev m0 = a.members[a.src[a.extra[g0]]];
+    const long long plane = (long long)m0.nx * m0.ny;
+    const long long total = 9 * plane;
+    const long long e0 = 4 * ((long long)blockIdx.x * 256 + threadIdx.x);
+    if (e0 >= total) return;
+    const bool pert = a.n_snap > 0 && a.mode[a.extra[g0]] == MODE_PERTURB;  // all copies alike
+    if ((plane & 3) == 0) {
+        double ad[PLACE_GROUP][4];
+#pragma unroll
+        for (int g = 0; g < PLACE_GROUP; ++g)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ad[g][k] = 0.0;
+        if (pert) {
+            for (int q = 0; q < a.n_snap; ++q) {
+                const f4g sv = *(const f4g*)(a.snapshots + (long long)q * total + e0);
+#pragma unroll
+                for (int g = 0; g < PLACE_GROUP; ++g) {
+                    if (g >= ng) break;
+                    const double al = a.alpha[(long long)a.extra[g0 + g] * MAX_SNAP + q];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) ad[g][k] = perturb_acc(ad[g][k], al, sv[k]);
+                }
+            }
+        }
+        const int i = (int)(e0 / plane);
+        // the group's source words first: the stores below may alias them as far as
+        // the compiler knows, so loads after a store would wait for it
+        f4g vs[PLACE_GROUP];
+#pragma unroll
+        for (int g = 0; g < PLACE_GROUP; ++g) {
+            if (g >= ng) break;
+            const int src = a.src[a.extra[g0 + g]];
+            vs[g] = *(const f4g*)((a.parity[src] ? a.pop1 : a.pop0) + a.members[src].off + e0);
+        }
+#pragma unroll
+        for (int g = 0; g < PLACE_GROUP; ++g) {
+            if (g >= ng) break;
+            const int m = a.extra[g0 + g];
+            float* const buf = a.parity[a.src[m]] ? a.pop1 : a.pop0;
+            const f4g v = vs[g];
+            f4g out = v;
+            if (pert) {
+                const double s = a.scale[m], cw = a.coef_w[m] * WD[i], eps = a.eps;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) out[k] = perturb_out(v[k], ad[g][k], s, eps, cw);
+            }
+            __builtin_nontemporal_store(out, (f4g*)(buf + a.new_off[m] + e0));
+        }
+        return;
+    }
+    const int cnt = (int)min((long long)4, total - e0);
+    for (int g = 0; g < ng; ++g) {
+        const int m = a.extra[g0 + g];
+        const int src = a.src[m];
+        float* const buf = a.parity[src] ? a.pop1 : a.pop0;
+        const float* sp = buf + a.members[src].off;
+        float* dp = buf + a.new_off[m];
+        for (int k = 0; k < cnt; ++k) {
+            const long long e = e0 + k;
+            if (!pert) {
+                dp[e] = sp[e];
+                continue;
+            }
+            const int i = (int)(e / plane);
+            double ad = 0.0;
+            for (int q = 0; q < a.n_snap; ++q)
+                ad = perturb_acc(ad, a.alpha[(long long)m * MAX_SNAP + q], a.snapshots[(long long)q * total + e]);
+            dp[e] = perturb_out(sp[e], ad, a.scale[m], a.eps, a.coef_w[m] * WD[i]);
+        }
+    }
+}
+
+// After the relabelling clone: every slot's block, buffer and flag.
+__global__ void clone_relabel_commit_kernel(CommitArgs a) {
+    const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (m >= a.n) return;
+    a.members[m].off = a.new_off[m];
+    a.parity[m] = a.new_parity[m];
+    a.accum[m] = 0.0;
+    a.flags[m] = a.flags_new[m];
+}
+
+hipError_t launch_place(const PlaceArgs& a, long long floats_per_member, hipStream_t st) {
+    if (a.n_extra == 0) return hipSuccess;
+    const unsigned gx = (unsigned)((floats_per_member / 4 + 255) / 256 + 1);
+    hipLaunchKernelGGL(clone_place_kernel, dim3(gx, (a.n_extra + PLACE_GROUP - 1) / PLACE_GROUP), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_relabel_commit(const FinishArgs& f, const CommitArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(clone_finish_kernel, dim3((f.n + 255) / 256), dim3(256), 0, st, f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(clone_relabel_commit_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_select(const SelectArgs& a, hipStream_t st) {

@@ -268,7 +268,7 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
         m.open = 0;
         m.gx0 = m.bar = 0;
         m.sp_x0 = d.nx;
-        m.pad_ = 0;
+        m.out_rho = 0;
         m.tau = m.tau_sp = d.tau;
         m.sp_inv = 0.0;
         m.u_c = 0.0;
@@ -640,7 +640,8 @@ static int validate_open(const lbm_member_desc& d, int i, const lbm_open_channel
 extern "C" int lbm_set_open_channel(lbm_ctx* c, const lbm_open_channel* oc) {
     if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     if (oc) {
-        if (oc->reserved != 0) return lbm_fail(LBM_EINVAL, "reserved field must be 0");
+        if (oc->outlet_density != 0 && oc->outlet_density != 1)
+            return lbm_fail(LBM_EINVAL, "outlet_density must be 0 (held at 1) or 1 (extrapolated)");
         if (!std::isfinite(oc->u_c) || oc->u_c < 0.0 || oc->u_c > 0.3)
             return lbm_fail(LBM_EINVAL, "inlet centre-line velocity must be in [0, 0.3]");
         if (oc->grid_bar < 0) return lbm_fail(LBM_EINVAL, "negative grid bar size");
@@ -668,6 +669,7 @@ extern "C" int lbm_set_open_channel(lbm_ctx* c, const lbm_open_channel* oc) {
         md.tau_sp = oc ? oc->sponge_tau : d.tau;
         md.sp_inv = md.sp_x0 < d.nx - 1 ? 1.0 / (double)(d.nx - 1 - md.sp_x0) : 0.0;
         md.u_c = oc ? oc->u_c : 0.0;
+        md.out_rho = oc ? oc->outlet_density : 0;
         md.ghost_off = goff;
         goff += 9LL * d.ny;
     }

@@ -250,6 +250,22 @@ __device__ __forceinline__ void stored_velocity(const float dl[9], double& ux, d
     uy = (((d[2] - d[4]) + (d[5] - d[7])) + (d[6] - d[8])) * inv;
 }
 
+// Open channel outlet, density extrapolated to second order (paper Section 2):
+// rho_g = 2 rho(nx-1) - rho(nx-2) of one row from the two stored cells, as
+// 1 + (2 sum d(nx-1) - sum d(nx-2)) so that the O(1) weights never enter the
+// sums; 1 when the member's outlet holds its density.
+__device__ __forceinline__ double outlet_density(const MemberDev& m, const float d1[9], const float d2[9]) {
+#pragma clang fp contract(off)
+    if (!m.out_rho) return 1.0;
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        s1 += (double)d1[i];
+        s2 += (double)d2[i];
+    }
+    return 1.0 + (2.0 * s1 - s2);
+}
+
 // The velocities of the last two columns of one row: (ux1, uy1) at nx - 1,
 // (ux2, uy2) at nx - 2.
 struct OutletVel {
@@ -258,20 +274,23 @@ struct OutletVel {
 
 // Outlet ghost population of a direction with c_x = -1 at row y, as a
 // deviation from its weight w:
-//   rho_g = 1,  u_g = 2 u(nx-1) - u(nx-2),
+//   rho_g = 1 or the extrapolated density (outlet_density),
+//   u_g = 2 u(nx-1) - u(nx-2),
 //   S_xx = ux(nx-1) - ux(nx-2),  S_yy = d_y uy_g,
 //   S_xy = (d_y ux_g + uy(nx-1) - uy(nx-2)) / 2
 //   (d_y centred over rows ya = y - 1 and yb = y + 1, one-sided in the first
 //   and last row, where the caller passes ya = y or yb = y),
-//   Pi = -2 c_s^2 (tau(nx-1) - 1) S,
-//   g_i = f_i^eq(1, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) : Pi.
+//   Pi = -2 rho_g c_s^2 (tau(nx-1) - 1) S,
+//   g_i = f_i^eq(rho_g, u_g) + w_i / (2 c_s^4) (c_i c_i - c_s^2 I) : Pi,
+//   i.e. g_i - w_i = w_i [(rho_g - 1) + rho_g X] with X the bracket for rho_g = 1.
 // The ghost kernel and the two-step kernel both build the ghost column with
 // this function; contraction into FMAs is off so that both give the same bits
 // wherever they are inlined.
 // (cx, cy, w: the direction's velocity and weight, passed as values so that
 // lanes can build different directions at once.)
 __device__ __forceinline__ float outlet_ghost_value(const MemberDev& m, double cx, double cy, double w, int y,
-                                                    const OutletVel& va, const OutletVel& v0, const OutletVel& vb) {
+                                                    const OutletVel& va, const OutletVel& v0, const OutletVel& vb,
+                                                    double rho_g) {
 #pragma clang fp contract(off)
     const double h = (y > 0 && y + 1 < m.ny) ? 0.5 : 1.0;  // centred or one-sided
     const double ux = 2.0 * v0.ux1 - v0.ux2, uy = 2.0 * v0.uy1 - v0.uy2;
@@ -286,7 +305,9 @@ __device__ __forceinline__ float outlet_ghost_value(const MemberDev& m, double c
     const double usq = ux * ux + uy * uy;
     const double cu = cx * ux + cy * uy;
     const double q = (cx * cx - 1.0 / 3.0) * pxx + 2.0 * cx * cy * pxy + (cy * cy - 1.0 / 3.0) * pyy;
-    return (float)(w * ((3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q));
+    const double x = (3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * q;
+    if (!m.out_rho) return (float)(w * x);
+    return (float)(w * ((rho_g - 1.0) + rho_g * x));
 }
 
 // Directions of (x, y) whose next cell lies in the square (x-moving ones only).

@@ -277,10 +277,21 @@ __global__ __launch_bounds__(256) void outlet_ghost_kernel(GhostArgs a) {
     float* __restrict__ g = a.ghost + m.ghost_off;
     for (int y = (int)threadIdx.x; y < ny; y += 256) {
         const OutletVel va = vel[y > 0 ? y - 1 : 0], v0 = vel[y], vb = vel[y + 1 < ny ? y + 1 : ny - 1];
+        double rho_g = 1.0;
+        if (m.out_rho) {  // the row's two cells again (the LDS table keeps velocities only)
+            float d1[9], d2[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const unsigned row = (unsigned)i * plane + (unsigned)y * (unsigned)nx;
+                d1[i] = src[row + (unsigned)(nx - 1)];
+                d2[i] = src[row + (unsigned)(nx - 2)];
+            }
+            rho_g = outlet_density(m, d1, d2);
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             if (CX[i] == 1) g[i * ny + y] = inlet_dev(m, i, y);
-            else if (CX[i] == -1) g[i * ny + y] = outlet_ghost_value(m, CX[i], CY[i], WD[i], y, va, v0, vb);
+            else if (CX[i] == -1) g[i * ny + y] = outlet_ghost_value(m, CX[i], CY[i], WD[i], y, va, v0, vb, rho_g);
         }
     }
 }

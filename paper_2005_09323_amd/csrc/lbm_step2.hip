@@ -121,6 +121,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     constexpr int RROWS = NW + 1 + LAG;        // ring rows: y - LAG - 1 .. y for the whole workgroup
     __shared__ f4 ring4[RROWS * 9 * RING_ROW / 4];
     __shared__ OutletVel vring[OPEN ? VROWS : 1];
+    __shared__ double rring[OPEN ? VROWS : 1];  // the rows' outlet densities (1 when held)
     float* const ring = (float*)ring4;
     const int b = a.xcd ? xcd_remap((int)blockIdx.x, a.total_blocks) : (int)blockIdx.x;
     int tx, ty, vec, seg_rows;
@@ -299,6 +300,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 stored_velocity(d1, v.ux1, v.uy1);
                 stored_velocity(d2, v.ux2, v.uy2);
                 vring[y & (VROWS - 1)] = v;
+                rring[y & (VROWS - 1)] = outlet_density(m, d1, d2);
             }
             // the outside cells (their drag belongs to the neighbouring strip)
             if (own_h) {
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         const OutletVel va = vring[(rsrc > 0 ? rsrc - 1 : 0) & (VROWS - 1)];
                         const OutletVel v0 = vring[rsrc & (VROWS - 1)];
                         const OutletVel vb = vring[(rsrc + 1 < ny ? rsrc + 1 : ny - 1) & (VROWS - 1)];
-                        h = outlet_ghost_value(m, CX[i], CY[i], WD[i], rsrc, va, v0, vb);
+                        h = outlet_ghost_value(m, CX[i], CY[i], WD[i], rsrc, va, v0, vb, rring[rsrc & (VROWS - 1)]);
                     } else {
                         h = srow[RING_RIGHT];
                     }

@@ -30,7 +30,14 @@ static int ensure_rare_scratch(lbm_ctx* c) {
         (e = hipMalloc(&r.need_mass, sizeof(int) * n)) != hipSuccess ||
         (e = hipMalloc(&r.flags_new, sizeof(int) * n)) != hipSuccess ||
         (e = hipHostMalloc(&r.status_host, sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&r.status, sizeof(int))) != hipSuccess)
+        (e = hipMalloc(&r.status, sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&r.new_off, sizeof(long long) * n)) != hipSuccess ||
+        (e = hipMalloc(&r.new_parity, sizeof(int) * n)) != hipSuccess ||
+        (e = hipMalloc(&r.extra, sizeof(int) * n)) != hipSuccess ||
+        (e = hipMalloc(&r.n_extra, sizeof(int))) != hipSuccess ||
+        (e = hipHostMalloc(&r.new_off_host, sizeof(long long) * n)) != hipSuccess ||
+        (e = hipHostMalloc(&r.new_parity_host, sizeof(int) * n)) != hipSuccess ||
+        (e = hipHostMalloc(&r.n_extra_host, sizeof(int))) != hipSuccess)
         return lbm_hip_fail(e, "allocation of cloning scratch");
     r.ready = true;
     return LBM_OK;
@@ -49,12 +56,20 @@ void free_rare_scratch(lbm_ctx* c) {
     hipFree(r.need_mass);
     hipFree(r.flags_new);
     hipFree(r.status);
+    hipFree(r.new_off);
+    hipFree(r.new_parity);
+    hipFree(r.extra);
+    hipFree(r.n_extra);
     if (r.status_host) hipHostFree(r.status_host);
+    if (r.new_off_host) hipHostFree(r.new_off_host);
+    if (r.new_parity_host) hipHostFree(r.new_parity_host);
+    if (r.n_extra_host) hipHostFree(r.n_extra_host);
     r = RareScratch();
 }
 
-// Mass partials, scales and the gather for the modes already in r.mode/r.src.
-static int run_gather(lbm_ctx* c, double eps, const float* snapshots, int n_snap, int reset_accum) {
+// Mass partials of the perturbed copies' parents and of the snapshots, and
+// each perturbed copy's scale, for the modes already in r.mode/r.src.
+static int run_mass_scale(lbm_ctx* c, double eps, const float* snapshots, int n_snap) {
     RareScratch& r = c->rare;
     hipError_t e;
     if (n_snap > 0 && eps != 0.0) {
@@ -89,6 +104,15 @@ static int run_gather(lbm_ctx* c, double eps, const float* snapshots, int n_snap
         sa.blocks_per_state = r.blocks_per_state;
         if ((e = launch_scale(sa, c->stream)) != hipSuccess) return lbm_hip_fail(e, "scale kernel");
     }
+    return LBM_OK;
+}
+
+// Mass partials, scales and the gather for the modes already in r.mode/r.src.
+static int run_gather(lbm_ctx* c, double eps, const float* snapshots, int n_snap, int reset_accum) {
+    RareScratch& r = c->rare;
+    hipError_t e;
+    int rc = run_mass_scale(c, eps, snapshots, n_snap);
+    if (rc) return rc;
     GatherArgs ga;
     ga.members = c->d_members;
     ga.parity = c->d_parity;
@@ -153,15 +177,87 @@ extern "C" int gktl_select_clone(lbm_ctx* c, double k, uint64_t key, int32_t per
     sa.need_mass = r.need_mass;
     sa.alpha = r.alpha;
     sa.alpha_sum = r.alpha_sum;
+    sa.members = c->d_members;
+    sa.parity = c->d_parity;
+    sa.relabel = c->relabel;
+    sa.new_off = r.new_off;
+    sa.new_parity = r.new_parity;
+    sa.extra = r.extra;
+    sa.n_extra = r.n_extra;
     hipError_t e;
     if ((e = launch_select(sa, c->stream)) != hipSuccess) return lbm_hip_fail(e, "selection kernel");
-    // the all-non-finite case must leave the ensemble untouched: read the status (synchronises)
-    if ((e = hipMemcpyAsync(r.status_host, r.status, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    // the all-non-finite case must leave the ensemble untouched: read the status (synchronises);
+    // relabelling also reads back where every slot's state goes (the host mirrors follow it)
+    const int n = c->n;
+    if ((e = hipMemcpyAsync(r.status_host, r.status, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
         return lbm_hip_fail(e, "selection status");
+    if (c->relabel &&
+        ((e = hipMemcpyAsync(r.n_extra_host, r.n_extra, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+         (e = hipMemcpyAsync(r.new_off_host, r.new_off, sizeof(long long) * n, hipMemcpyDeviceToHost, c->stream)) !=
+             hipSuccess ||
+         (e = hipMemcpyAsync(r.new_parity_host, r.new_parity, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream)) !=
+             hipSuccess))
+        return lbm_hip_fail(e, "selection tables");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return lbm_hip_fail(e, "selection status");
     if (*r.status_host != 0) return lbm_fail(LBM_ENONFINITE, "every trajectory has a non-finite weight");
-    if ((rc = run_gather(c, eps, snapshots, n_snap, 1))) return rc;
-    for (int m = 0; m < c->n; ++m) c->h_parity[m] ^= 1;
+    if (!c->relabel) {
+        if ((rc = run_gather(c, eps, snapshots, n_snap, 1))) return rc;
+        for (int m = 0; m < n; ++m) c->h_parity[m] ^= 1;
+        return LBM_OK;
+    }
+    // relabelling: the first copy of every ancestor keeps its block; the other
+    // copies are written into blocks whose states left no descendant
+    if ((rc = run_mass_scale(c, eps, snapshots, n_snap))) return rc;
+    PlaceArgs pa;
+    pa.members = c->d_members;
+    pa.parity = c->d_parity;
+    pa.extra = r.extra;
+    pa.src = r.src;
+    pa.mode = r.mode;
+    pa.new_off = r.new_off;
+    pa.pop0 = c->pop[0];
+    pa.pop1 = c->pop[1];
+    pa.snapshots = snapshots;
+    pa.alpha = r.alpha;
+    pa.scale = r.scale;
+    pa.coef_w = r.coef_w;
+    pa.eps = eps;
+    pa.n_snap = (eps != 0.0) ? n_snap : 0;
+    pa.n_extra = *r.n_extra_host;
+    if (pa.n_extra < 0 || pa.n_extra > n)
+        return lbm_fail(LBM_EHIP, "selection reported %d further copies of %d", pa.n_extra, n);
+    if ((e = launch_place(pa, 9LL * c->h_members[0].nx * c->h_members[0].ny, c->stream)) != hipSuccess)
+        return lbm_hip_fail(e, "placement kernel");
+    FinishArgs fa;
+    fa.mode = r.mode;
+    fa.src = r.src;
+    fa.parity = c->d_parity;
+    fa.accum = c->accum;
+    fa.flags = c->d_flags;
+    fa.flags_new = r.flags_new;
+    fa.n = n;
+    fa.reset_accum = 1;
+    CommitArgs ca;
+    ca.members = c->d_members;
+    ca.parity = c->d_parity;
+    ca.new_off = r.new_off;
+    ca.new_parity = r.new_parity;
+    ca.accum = c->accum;
+    ca.flags = c->d_flags;
+    ca.flags_new = r.flags_new;
+    ca.n = n;
+    if ((e = launch_relabel_commit(fa, ca, c->stream)) != hipSuccess) return lbm_hip_fail(e, "relabelling commit");
+    for (int m = 0; m < n; ++m) {
+        c->h_members[m].off = r.new_off_host[m];
+        c->h_parity[m] = r.new_parity_host[m];
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_cloning(lbm_ctx* c, int32_t relabel) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (relabel != 0 && relabel != 1) return lbm_fail(LBM_EINVAL, "relabel must be 0 or 1");
+    c->relabel = relabel;
     return LBM_OK;
 }
 

@@ -16,6 +16,13 @@ struct MaskWords {
 };
 
 struct SelectArgs {
+    const MemberDev* members;  // current blocks (off) of the states
+    const int* parity;         // current parities
+    int relabel;        // 1: place copies by relabelling blocks (tables below), 0: gather every copy
+    long long* new_off; // [n] out (relabel): the block each slot's state occupies after the clone
+    int* new_parity;    // [n] out (relabel): its buffer
+    int* extra;         // [n] out (relabel): slots whose state is written (copies beyond the first), in order
+    int* n_extra;       // [1] out (relabel)
     const double* accum;
     double k;
     uint64_t key;
@@ -90,6 +97,38 @@ struct GatherArgs {
     int n_snap;
 };
 
+// Relabelling clone: the copies beyond the first of each ancestor, written
+// into the blocks of states that left no descendant (same buffer as the
+// ancestor); the first copy of each ancestor keeps the ancestor's block.
+struct PlaceArgs {
+    const MemberDev* members;  // blocks before the clone (the ancestors' states)
+    const int* parity;         // parities before the clone
+    const int* extra;          // [n_extra] slots to write
+    const int* src;            // [n] ancestor of each slot
+    const int* mode;           // [n] MODE_COPY or MODE_PERTURB
+    const long long* new_off;  // [n] destination block of each slot
+    float* pop0;
+    float* pop1;
+    const float* snapshots;
+    const double* alpha;
+    const double* scale;
+    const double* coef_w;
+    double eps;
+    int n_snap;
+    int n_extra;  // entries of extra
+};
+
+struct CommitArgs {
+    MemberDev* members;
+    int* parity;
+    const long long* new_off;
+    const int* new_parity;
+    double* accum;
+    int* flags;
+    const int* flags_new;
+    int n;
+};
+
 struct FinishArgs {
     const int* mode;
     const int* src;
@@ -107,5 +146,8 @@ hipError_t launch_mass(const MassArgs& a, int n_states, hipStream_t st);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t st);
 hipError_t launch_gather(const GatherArgs& a, long long floats_per_member, hipStream_t st);
 hipError_t launch_finish(const FinishArgs& a, hipStream_t st);
+hipError_t launch_place(const PlaceArgs& a, long long floats_per_member, hipStream_t st);
+// flags_new[m] = flags[src[m]] (before any flag changes), then the commit
+hipError_t launch_relabel_commit(const FinishArgs& f, const CommitArgs& a, hipStream_t st);
 
 }  // namespace lbm

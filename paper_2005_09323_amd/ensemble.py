@@ -130,15 +130,22 @@ class Ensemble:
         self._collision = (model, float(s_bulk), float(s_third), float(s_fourth))
 
     def set_open_channel(self, u_c: Optional[float], grid_x0: int = 0, grid_bar: int = 0,
-                         sponge_x0: int = 1 << 30, sponge_tau: float = 1.0) -> None:
-        """Inlet, entrance grid, sponge and outlet instead of periodic x (None: periodic); before init."""
+                         sponge_x0: int = 1 << 30, sponge_tau: float = 1.0, outlet_density: int = 0) -> None:
+        """Inlet, entrance grid, sponge and outlet instead of periodic x (None: periodic); before init.
+        outlet_density: 0 holds the outlet's density at 1, 1 extrapolates it to second order."""
         if u_c is None:
             native.check(self.lib.lbm_set_open_channel(self._ctx, None))
             self._open = None
             return
-        oc = native.OpenChannelDesc(u_c, grid_x0, grid_bar, sponge_x0, 0, sponge_tau)
+        oc = native.OpenChannelDesc(u_c, grid_x0, grid_bar, sponge_x0, outlet_density, sponge_tau)
         native.check(self.lib.lbm_set_open_channel(self._ctx, ctypes.byref(oc)))
-        self._open = (float(u_c), int(grid_x0), int(grid_bar), int(sponge_x0), float(sponge_tau))
+        self._open = (float(u_c), int(grid_x0), int(grid_bar), int(sponge_x0), float(sponge_tau),
+                      int(outlet_density))
+
+    def set_cloning(self, relabel: bool) -> None:
+        """GKTL copies by relabelling member blocks (default: only copies beyond the first of each
+        ancestor move data) or by gathering every copy into the other buffer; same results."""
+        native.check(self.lib.lbm_set_cloning(self._ctx, 1 if relabel else 0))
 
     def set_graphs(self, on: bool) -> None:
         """Replay full 64-step chunks from a captured HIP graph (default) or launch every kernel."""

@@ -37,7 +37,8 @@ class MemberDesc(ctypes.Structure):
 
 class OpenChannelDesc(ctypes.Structure):
     _fields_ = [("u_c", ctypes.c_double), ("grid_x0", ctypes.c_int32), ("grid_bar", ctypes.c_int32),
-                ("sponge_x0", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sponge_tau", ctypes.c_double)]
+                ("sponge_x0", ctypes.c_int32), ("outlet_density", ctypes.c_int32),
+                ("sponge_tau", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -69,6 +70,7 @@ _SIG = {
     "lbm_autotune": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),
     "lbm_autotune_cached": (ctypes.c_int, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_I)]),
     "gktl_select_clone": (ctypes.c_int, [_P, _D, _U64, _I, _D, _P, _I, _P, _P]),
+    "lbm_set_cloning": (ctypes.c_int, [_P, _I]),
     "lbm_perturb": (ctypes.c_int, [_P, _P, _U64, _I, _D, _P, _I]),
     "lbm_copy_state_out": (ctypes.c_int, [_P, _I, _P]),
     "lbm_copy_state_in": (ctypes.c_int, [_P, _I, _P, _I]),

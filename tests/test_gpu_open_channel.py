@@ -25,13 +25,13 @@ def _ensemble(members, cap, op, collision=None, tile=None):
         ens.set_tile(tile)
     if collision is not None:
         ens.set_collision("central", *collision)
-    ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau)
+    ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau, op.outlet_rho)
     return ens
 
 
 def _channel(m, op, collision=None):
     return olbm.Channel(m.nx, m.ny, m.tau, m.force_x, m.square, collision,
-                        open=OpenChannel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau))
+                        open=OpenChannel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau, op.outlet_rho))
 
 
 def _oracle(m, op, seed, member_index, amp, steps, collision=None):
@@ -53,9 +53,11 @@ MEMBERS = [workloads.Member(192, 48, 0.56, 0.0, (70, 19, 8)),
            workloads.Member(130, 40, 0.6, 2e-6, (50, 16, 6))]
 OPEN = workloads.OpenParams(0.05, 12, 6, 150 - 40, 0.95)  # sponge over the last ~40 / ~20 columns
 OPEN_ODD = workloads.OpenParams(0.04, 9, 5, 100, 0.8)      # odd bar (half gap of 2 rows), longer sponge
+OPEN_RHO = workloads.OpenParams(0.05, 12, 6, 150 - 40, 0.95, outlet_rho=1)  # outlet density extrapolated
 
 
-@pytest.mark.parametrize("collision,op", [(None, OPEN), (CM_RATES, OPEN), (None, OPEN_ODD)])
+@pytest.mark.parametrize("collision,op", [(None, OPEN), (CM_RATES, OPEN), (None, OPEN_ODD),
+                                          (None, OPEN_RHO), (CM_RATES, OPEN_RHO)])
 def test_open_channel_against_oracle(collision, op):
     steps = 1000
     ens = _ensemble(MEMBERS, steps, op, collision)
@@ -116,24 +118,32 @@ def test_open_channel_inactive_members_frozen():
     ens.close()
 
 
+def _golden(name):
+    import os
+    return np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name))
+
+
 def test_paper_open_channel_sampled_members():
     """The paper's channel (512 x 128, R = 16, grid of R/2 bars, sponge), central moments, the
-    full 1024-member ensemble in the launch configuration of the benchmark: two sampled members
-    against the oracle over 200 steps."""
+    full 1024-member ensemble in the launch configuration of the benchmark (two steps per
+    launch): members 0, 777 and 1023 against the stored oracle series over 2000 steps, and every
+    member finite."""
     wl = workloads.open_channel()
     op, rates = wl.extra["open"], wl.extra["rates"]
-    steps = 200
+    steps = 2000
     ens = _ensemble(wl.members, steps, op, rates)
+    assert ens.launch_steps() == 2
     ens.init(wl.seed, wl.noise_amp)
     ens.step(steps - 1)
     torch.cuda.synchronize()
-    sample = (0, 777)
+    sample = (0, 777, 1023)
     drag = ens.drag(0, steps).cpu().numpy()[list(sample)]
     assert int(ens.flags().sum()) == 0
     ens.close()
     torch.cuda.empty_cache()
     for k, i in enumerate(sample):
-        _, _, ref = _oracle(wl.members[i], op, wl.seed, i, wl.noise_amp, steps, rates)
+        ref = _golden(f"open1024_m{i}_drag2000.txt")
+        print(f"member {i}: drag rel err {_rel(drag[k], ref):.2e} over {steps} steps")
         assert _rel(drag[k], ref) <= 1e-5, (i, _rel(drag[k], ref))
 
 
@@ -154,6 +164,11 @@ def test_open_channel_argument_errors():
     ens = Ensemble([near_outlet], series_capacity=10)
     with pytest.raises(LbmError):
         ens.set_open_channel(0.05)
+    ens.close()
+    ens = Ensemble([m], series_capacity=10)
+    for mode in (-1, 2):
+        with pytest.raises(LbmError):
+            ens.set_open_channel(0.05, 12, 6, 150, 0.9, outlet_density=mode)
     ens.close()
     ens = _ensemble([m], 10, OPEN)
     with pytest.raises(LbmError):
@@ -259,8 +274,8 @@ def test_gktl_run_on_open_channel_matches_oracle():
     ens.close()
 
 
-@pytest.mark.parametrize("collision", [None, CM_RATES])
-def test_open_channel_two_step_bit_identical_to_one_step(collision):
+@pytest.mark.parametrize("collision,outlet_rho", [(None, 0), (CM_RATES, 0), (None, 1), (CM_RATES, 1)])
+def test_open_channel_two_step_bit_identical_to_one_step(collision, outlet_rho):
     """Widths that are multiples of 256: the two-step kernel (inlet values from the ghost block,
     the outlet ghost column of its second step built in the kernel) against the one-step shape 0,
     bit for bit; a single-strip lattice (inlet and outlet in one strip), grid bars across a strip
@@ -268,11 +283,11 @@ def test_open_channel_two_step_bit_identical_to_one_step(collision):
     members = [workloads.Member(512, 40, 0.56, 0.0, (200, 15, 8)),
                workloads.Member(512, 40, 0.6, 1e-6, (300, 10, 6)),
                workloads.Member(512, 40, 0.56, 0.0, (200, 15, 8))]
-    op = workloads.OpenParams(0.05, 20, 6, 400, 0.9)
+    op = workloads.OpenParams(0.05, 20, 6, 400, 0.9, outlet_rho)
     single = [workloads.Member(256, 33, 0.58, 0.0, (100, 12, 8))]
-    op_single = workloads.OpenParams(0.04, 30, 4, 200, 0.8)
+    op_single = workloads.OpenParams(0.04, 30, 4, 200, 0.8, outlet_rho)
     straddle = [workloads.Member(512, 40, 0.56, 0.0, (300, 15, 8))] * 2
-    op_straddle = workloads.OpenParams(0.05, 252, 8, 300, 0.9)  # grid bars across the strip seam at x = 256
+    op_straddle = workloads.OpenParams(0.05, 252, 8, 300, 0.9, outlet_rho)  # grid bars across the strip seam
     steps = 151
     for mem, o in ((members, op), (single, op_single), (straddle, op_straddle)):
         runs = {}

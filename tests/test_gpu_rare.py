@@ -451,3 +451,47 @@ def test_learned_score_argument_errors():
     for level, width in ((float("nan"), 1.0), (1.0, 0.0), (1.0, -1.0), (1.0, float("inf"))):
         rc = native.lib().ams_learned_score(_ptr(g), _ptr(g), 4, level, width, _ptr(g), _stream_handle(None))
         assert rc == native.LBM_EINVAL
+
+
+@pytest.mark.parametrize("eps,n_snap", [(0.002, 10), (0.0, 0)])
+def test_relabelling_clone_bit_identical_to_gather(eps, n_snap):
+    """GKTL cloning by relabelling member blocks (the default: the first copy of an ancestor moves
+    no data) against gathering every copy into the other buffer: ancestors, states, drag series and
+    integrals bit for bit over six periods of 128 steps (two-step kernel, graph replays), with the
+    perturbation and with eps = 0 (further copies are plain copies).  The members' blocks stay a
+    permutation of the canonical ones."""
+    m = workloads.Member(256, 32, 0.56, 2e-5, (60, 12, 8))
+    n, tau, periods = 48, 128, 6
+    snaps = torch.from_numpy(workloads.snapshot_states(max(n_snap, 1), m, 3)).cuda()[:n_snap].contiguous()
+    runs = {}
+    for relabel in (True, False):
+        ens = _ens([m] * n, cap=tau * periods + 10)
+        ens.set_tile(16)  # two steps per launch over whole strips
+        ens.set_cloning(relabel)
+        ens.init(17, 1e-2)
+        ens.set_observable(0.0, 1e-4, 1.0 / 64)
+        ancs, ints = [], []
+        for p in range(periods):
+            ens.step(tau)
+            ints.append(ens.accum.clone())
+            anc, _ = ens.gktl_select_clone(1.0, key=5, period=p, eps=eps, snapshots=snaps if n_snap else None)
+            ancs.append(anc.clone())
+        ens.step(7)  # an odd step after the last clone
+        torch.cuda.synchronize()
+        fluid = torch.from_numpy(~olbm.solid_mask(_channel(m))).cuda()
+        ptrs = sorted(ens.state(i).data_ptr() for i in range(n))
+        runs[relabel] = (torch.stack(ancs).cpu(), torch.stack(ints).cpu(), ens.drag(0, ens.time()).cpu(),
+                         torch.stack([ens.state(i)[:, fluid] for i in range(n)]).cpu(), ptrs, ens)
+    a1, i1, d1, s1, p1, e1 = runs[True]
+    a0, i0, d0, s0, p0, e0 = runs[False]
+    assert len(set(a1[0].tolist())) < n            # lineages were cut and copied
+    assert torch.equal(a1, a0) and torch.equal(i1, i0)
+    assert torch.equal(d1, d0) and torch.equal(s1, s0)
+    # every block in use exactly once (offsets within a buffer are a permutation)
+    floats = 9 * m.nx * m.ny
+    for ens, ptrs in ((e1, p1), (e0, p0)):
+        offs = sorted(((p - ens.pop_a.data_ptr()) if ens.pop_a.data_ptr() <= p < ens.pop_a.data_ptr() + ens.pop_a.numel() * 4
+                       else (p - ens.pop_b.data_ptr())) // 4 for p in ptrs)
+        assert offs == [k * floats for k in range(n)]
+    e1.close()
+    e0.close()

@@ -5,6 +5,7 @@ sponge ramp."""
 import math
 
 import numpy as np
+import pytest
 
 from oracle import lbm
 from oracle.open_channel import OpenChannel, grid_mask, inlet_ghost, inlet_velocity, outlet_ghost, tau_field
@@ -41,8 +42,9 @@ def _ghost_mass_balance(ch, fout):
     return math.fsum(gained)
 
 
-def test_streaming_mass_accounting():
-    ch = lbm.Channel(40, 16, 0.7, 0.0, (20, 5, 4), open=OpenChannel(0.03, 6, 4, 30, 0.9))
+@pytest.mark.parametrize("outlet_rho", [0, 1])
+def test_streaming_mass_accounting(outlet_rho):
+    ch = lbm.Channel(40, 16, 0.7, 0.0, (20, 5, 4), open=OpenChannel(0.03, 6, 4, 30, 0.9, outlet_rho))
     f = _start(ch)
     rng = np.random.default_rng(3)
     f = f * (1 + 0.01 * rng.standard_normal(f.shape))  # any state, not only steady ones
@@ -104,6 +106,68 @@ def test_outlet_ghost_moments():
     assert np.abs((cx * cx * neq).sum(axis=0) - (-2 / 3 * (tau - 1) * d)).max() < 1e-16  # value ~3e-4
     assert np.abs((cx * cy * neq).sum(axis=0)).max() < 1e-16
     assert np.abs((cy * cy * neq).sum(axis=0)).max() < 1e-16
+
+
+def test_outlet_ghost_moments_with_extrapolated_density():
+    """As above with the density extrapolated too: the ghost has density 2 rho(nx-1) - rho(nx-2)
+    = 1.01, velocity U + d, and a non-equilibrium xx moment of -2 c_s^2 rho_g (tau - 1) d."""
+    ny, nx, tau, U, d = 8, 20, 0.7, 0.04, 0.002
+    ch = lbm.Channel(nx, ny, tau, 0.0, None, open=OpenChannel(0.05, 0, 0, nx, tau, outlet_rho=1))
+    fo = np.zeros((9, ny, nx))
+    fo[:, :, nx - 1] = lbm.equilibrium(np.full(ny, 1.02), np.full(ny, U), np.zeros(ny))
+    fo[:, :, nx - 2] = lbm.equilibrium(np.full(ny, 1.03), np.full(ny, U - d), np.zeros(ny))
+    g = outlet_ghost(ch, fo)
+    rho_g = 2 * 1.02 - 1.03
+    assert np.abs(g.sum(axis=0) - rho_g).max() < 1e-15
+    neq = g - lbm.equilibrium(np.full(ny, rho_g), np.full(ny, U + d), np.zeros(ny))
+    cx, cy = lbm.C[:, 0][:, None], lbm.C[:, 1][:, None]
+    assert np.abs(neq.sum(axis=0)).max() < 1e-15
+    assert np.abs((cx * neq).sum(axis=0)).max() < 1e-15 and np.abs((cy * neq).sum(axis=0)).max() < 1e-15
+    assert np.abs((cx * cx * neq).sum(axis=0) - (-2 / 3 * rho_g * (tau - 1) * d)).max() < 1e-16
+    assert np.abs((cx * cy * neq).sum(axis=0)).max() < 1e-16
+    assert np.abs((cy * cy * neq).sum(axis=0)).max() < 1e-16
+
+
+def _developed(nx, ny, tau, outlet_rho, steps):
+    """Mean density and mid-channel momentum flux (per row) of the obstacle-free open channel
+    with the inlet centre-line velocity 0.05 after `steps` steps from the inlet profile."""
+    ch = lbm.Channel(nx, ny, tau, 0.0, None, open=OpenChannel(0.05, 0, 0, nx, tau, outlet_rho))
+    f = _start(ch)
+    for _ in range(steps):
+        f = lbm.stream(ch, lbm.collide(ch, f))
+    rho = f.sum(axis=0)
+    jx = (lbm.C[:, 0][:, None, None] * f).sum(axis=0)
+    return float(rho.mean()), float(jx[:, nx // 2].mean())
+
+
+def test_extrapolated_outlet_density_leaves_the_flow_rate_to_the_outlet():
+    """Why the outlet holds its density at 1 by default.  The inlet imposes the equilibrium of
+    unit density and the parabolic profile (mean flux u_in = 2/3 u_c per row).  With the density
+    at the outlet held at 1, the channel's mean density stays within 1.5 % of 1 and its flux
+    within 25 % of the inlet's.  With the density extrapolated to second order as well (the
+    paper's words), nothing fixes the pressure level: at tau 0.8 the channel fills (mean
+    density 1.109) until the flow stops, at tau 0.6 it drains (0.847) and carries more than
+    twice the flux, and at tau 0.52 with a square (128 x 32, side 8) it drains and blows up
+    within 4000 steps, where the held density stays within 0.2 % of 1."""
+    u_in = 2.0 / 3.0 * 0.05
+    r0, q0 = _developed(64, 16, 0.8, 0, 4000)
+    r1, q1 = _developed(64, 16, 0.8, 1, 4000)
+    assert abs(r0 - 1) < 0.015 and abs(q0 / u_in - 1) < 0.25, (r0, q0)
+    assert r1 > 1.09 and abs(q1) < 0.02 * u_in, (r1, q1)
+    r0, q0 = _developed(96, 24, 0.6, 0, 2000)
+    r1, q1 = _developed(96, 24, 0.6, 1, 2000)
+    assert abs(r0 - 1) < 0.015 and abs(q0 / u_in - 1) < 0.25, (r0, q0)
+    assert r1 < 0.87 and q1 > 2.0 * q0, (r1, q1, q0)
+    finals = []
+    for mode in (0, 1):
+        ch = lbm.Channel(128, 32, 0.52, 0.0, (32, 12, 8), open=OpenChannel(0.05, 0, 0, 128, 0.52, mode))
+        f = _start(ch)
+        with np.errstate(all="ignore"):
+            for _ in range(4000):
+                f = lbm.stream(ch, lbm.collide(ch, f))
+        finals.append(f[:, ~lbm.solid_mask(ch)].sum(axis=0))
+    assert np.all(np.isfinite(finals[0])) and abs(finals[0].mean() - 1) < 0.002
+    assert not np.all(np.isfinite(finals[1]))
 
 
 def test_grid_geometry():

@@ -115,6 +115,7 @@ class OpenParams:
     bar: int
     sponge_x0: int
     sponge_tau: float
+    outlet_rho: int = 0  # outlet density: 0 held at 1, 1 extrapolated to second order
 
 
 def open_channel(n_members: int = 1024) -> Workload:
