@@ -15,8 +15,12 @@ its maximum Q over [0, T_a].  One iteration (Appendix B.1):
   its first time t_b with xi(t_b) > level (strictly above, so the copy
   already beats the level), and is re-simulated from there (with a
   perturbation for deterministic dynamics).
-* stopping: after J iterations or once every maximum reaches the target
-  threshold.
+* stopping: after J iterations, once every maximum reaches the target
+  threshold, or once the level itself reaches it (with n_kill > 1 the
+  n_kill-th lowest maximum can reach the threshold before the lowest one
+  does; discarding at such a level would discard trajectories that reached
+  the event, and a score that stops at the threshold once the event has
+  happened would discard all of them).
 
 Estimator (the paper cites it without printing it): the standard unbiased
 generalised-AMS estimate of p(a) = P(max_{[0, T_a]} xi >= a) is
@@ -148,6 +152,8 @@ def run(init_paths: np.ndarray, resimulate: Callable, n_kill: int, key: int,
         if clean_maxima(xi).min() >= threshold:
             break
         kb = kill_branch(xi, n_kill, key, it)
+        if kb.level >= threshold:
+            break
         if kb.extinct:
             extinct = True
             break

@@ -37,12 +37,37 @@ class Flow:
     square: tuple = (120, 56, 16)
     u0: float = 0.02
     burn: int = 200_000
+    collision: str = "bgk"          # or "central" (central moments, unit higher-order rates)
 
     def ensemble(self, n: int, cap: int) -> "Ensemble":
-        return Ensemble([Member(self.nx, self.ny, self.tau, self.force_x, self.square)] * n, series_capacity=cap)
+        ens = Ensemble([Member(self.nx, self.ny, self.tau, self.force_x, self.square)] * n, series_capacity=cap)
+        if self.collision != "bgk":
+            ens.set_collision(self.collision, 1.0, 1.0, 1.0)
+        return ens
 
     def start(self, ens: "Ensemble", seed: int) -> None:
         ens.init(seed, 1e-3, ux0=self.u0)
+
+
+def gktl_flow() -> Flow:
+    """The GKTL workload's channel (1024 x 256, square 32 centred at (256, 128), tau 0.5015) with
+    central moments.  Its stated force density 3e-6 accelerates the flow past momentum 0.1 per
+    cell (Mach above 0.2) and every member blows up between 40 000 and 60 000 steps, with either
+    collision; 3e-7 keeps the mean momentum near 0.04 (Mach about 0.07, the low-Mach rule the
+    other workloads take their force from) and stays finite (measured over 2 x 10^5 steps,
+    correlation time about 3 500 steps).  Started at u = 0.05 to skip the acceleration."""
+    return Flow(nx=1024, ny=256, tau=0.5015, force_x=3e-7, square=(240, 112, 32), u0=0.05, burn=100_000,
+                collision="central")
+
+
+def ams_flow() -> Flow:
+    """The AMS workload's channel (512 x 128, square 16 centred at (128, 64), tau 0.502) with
+    central moments.  The workload gives no force; the Poiseuille rule (8 nu u_c / ny^2 =
+    1.6e-8) ignores the square's drag, and the flow it drives slows from 0.033 to a momentum of
+    0.007 per cell over 2 x 10^5 steps towards laminar shedding; 1e-6 keeps a chaotic,
+    stationary flow (momentum about 0.04 per cell, correlation time about 2 400 steps)."""
+    return Flow(nx=512, ny=128, tau=0.502, force_x=1e-6, square=(120, 56, 16), u0=0.05, burn=100_000,
+                collision="central")
 
 
 @dataclass
@@ -69,6 +94,17 @@ def _emit(out, rec: dict) -> None:
     if out:
         with open(out, "a") as fh:
             fh.write(line + "\n")
+
+
+def _step_with_progress(ens: Ensemble, steps: int, what: str, chunk: int = 20_000) -> None:
+    """ens.step(steps) in chunks, with a progress line after each (long runs stay audible)."""
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        ens.step(k)
+        done += k
+        torch.cuda.synchronize()
+        _progress(f"{what}: {done}/{steps} steps")
 
 
 def burn_in(flow, n: int, seed: int, cap: int) -> Ensemble:
@@ -159,9 +195,12 @@ def _distinct_roots(ancestors: torch.Tensor) -> int:
 
 def gktl_and_direct(flow, n: int, repeats: int, ks, out=None, seed: int = 100,
                     direct_steps: int = 200_000, eps: float = 0.002, clone_tc: float = 1.0,
-                    ta_windows: int = 2, n_src: int = 256):
+                    ta_windows: int = 2, n_src: int = 256, fixed: dict = None,
+                    zs=(1.5, 2.0, 2.5, 3.0, 3.5, 4.0)):
     """Direct-sampling reference from n_src stationary members, then GKTL repeats with n clones.
 
+    The cloning period, window T, trajectory length T_a and time step of the observable follow
+    the measured correlation time tau_c unless `fixed` gives them (keys tau, window, t_a, dt).
     Each repeat starts from the source states 2 tau_c further on; when n > n_src the extra
     members are perturbed copies, given 4 tau_c to separate before the run starts."""
     n_src = min(n, n_src)
@@ -170,13 +209,16 @@ def gktl_and_direct(flow, n: int, repeats: int, ks, out=None, seed: int = 100,
     tau = max(64, int(round(st.tau_c * clone_tc / 64)) * 64)  # cloning period in correlation times
     window = max(1, round(5 * st.tau_c / tau)) * tau           # T ~ 5 tau_c, a multiple of tau
     n_per = ta_windows * window // tau                         # T_a = ta_windows * T
-    t_a = n_per * tau
     dt = 1.0 / st.tau_c                                        # time in correlation times
+    if fixed:
+        tau, window, dt = fixed["tau"], fixed["window"], fixed["dt"]
+        n_per = fixed["t_a"] // tau
+    t_a = n_per * tau
     # direct reference from the source ensemble: long run cut into blocks of t_a
     direct_len = direct_steps // t_a * t_a
     t0 = _sync_time()
     src.set_time(1)
-    src.step(direct_len)
+    _step_with_progress(src, direct_len, "direct run")
     direct_wall = _sync_time() - t0
     _progress(f"direct run: {direct_len} steps x {n_src} members in {direct_wall:.1f} s")
     series = src.drag(1, 1 + direct_len).contiguous()
@@ -185,7 +227,7 @@ def gktl_and_direct(flow, n: int, repeats: int, ks, out=None, seed: int = 100,
     means = (cs[:, window:] - cs[:, :-window]) / window
     sig_t = float(means.std())
     mu_t = float(means.mean())
-    levels = [mu_t + z * sig_t for z in (1.5, 2.0, 2.5, 3.0, 3.5, 4.0)]
+    levels = [mu_t + z * sig_t for z in zs]
     p_dir, r_dir, _ = rare.direct_return_times(series, t_a, window, levels)
     n_blocks = n_src * (direct_len // t_a)
     step_cost = direct_wall / (n_src * direct_len)             # seconds per member-step
@@ -194,6 +236,7 @@ def gktl_and_direct(flow, n: int, repeats: int, ks, out=None, seed: int = 100,
         nb = (1 - p) / (p * 0.01) if p > 0 else math.inf      # blocks for 10 % relative error
         dir_wall10.append(nb * t_a * step_cost)
     _emit(out, {"experiment": "direct", "flow": asdict(flow), "n": n_src, "mu": st.mu, "sigma": st.sigma,
+                "direct_steps": direct_len, "direct_wall_s": direct_wall, "level_sigmas": list(zs),
                 "tau_c_steps": st.tau_c, "window_T": window, "t_a": t_a, "tau_clone": tau,
                 "mu_T": mu_t, "sigma_T": sig_t, "levels": levels, "blocks": n_blocks,
                 "p": p_dir.tolist(), "r_steps": r_dir.tolist(),
@@ -277,7 +320,7 @@ def train_score(flow, n: int, rounds: int, horizon: int, out=None, seed: int = 7
         else:
             parts.append(np.full(int(np.prod(shape)), mu if name == "b4" else 0.0))
     flat = np.concatenate(parts).astype(np.float32)
-    net = ScoreNet(torch.from_numpy(flat), 256)
+    net = ScoreNet(torch.from_numpy(flat), max(256, n))
     batch = 256
     t0 = _sync_time()
     steps = 0
@@ -306,7 +349,7 @@ def train_score(flow, n: int, rounds: int, horizon: int, out=None, seed: int = 7
 
 def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: int = 512,
                 rounds: int = 200, n_kill_frac: float = 1 / 16, max_iter: int = 400, eps: float = 0.002,
-                z: float = 5.0, direct_steps: int = 200_000):
+                z: float = 5.0, direct_steps: int = 200_000, scores=("plain", "learned")):
     """AMS with the plain score (the running window mean of the drag) and with the learned score,
     for the event max over [0, T_a] of the `window`-step mean drag >= mu + z sigma_window.  Each run
     stops once every trajectory has reached that level, so the estimate is for that level only."""
@@ -320,7 +363,7 @@ def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: i
     # direct-sampling reference on the same event: blocks of t_a steps of the stationary source
     direct_len = direct_steps // t_a * t_a
     src.set_time(1)
-    src.step(direct_len)
+    _step_with_progress(src, direct_len, "AMS direct reference")
     n_blocks = n * (direct_len // t_a)
     blocks = src.drag(1, 1 + direct_len).reshape(n_blocks, t_a).contiguous()
     stride = 32                                                # the AMS score grid
@@ -333,6 +376,8 @@ def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: i
                 "s_per_member_step": step_cost})
     snaps = _snapshots(src, 10)
     for name, use_net in (("plain", None), ("learned", net)):
+        if name not in scores:
+            continue
         probs, walls, costs, iters, extinct = [], [], [], [], 0
         ens = flow.ensemble(n, t_a + 2)
         for rep in range(repeats):
@@ -351,6 +396,8 @@ def ams_compare(flow, n: int, repeats: int, out=None, seed: int = 200, window: i
             extinct += int(res.extinct)
             probs.append(0.0 if res.extinct else res.probability([level])[0])
             _progress(f"ams {name} repeat {rep}: {walls[-1]:.2f} s, {iters[-1]} iterations, p={probs[-1]:.4g}")
+            _emit(out, {"experiment": "ams_run", "score": name, "repeat": rep, "p": probs[-1], "wall_s": walls[-1],
+                        "member_steps": costs[-1], "iterations": iters[-1], "extinct": bool(res.extinct)})
             del runner
             torch.cuda.empty_cache()
         probs = np.array(probs)
@@ -445,7 +492,10 @@ def open_channel_stats(flow: OpenFlow, n: int, burn: int, steps: int, out=None, 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["gktl", "ams", "all", "open", "score"])
+    ap.add_argument("which", choices=["gktl", "ams", "all", "open", "score", "cfg3", "cfg4"],
+                    help="cfg3: GKTL on the 256 x 1024 x 256 workload (period 256, T 2048, T_a 6144, "
+                         "k 0.5/1/2, dt 1/512); cfg4: AMS with the plain and the learned score on the "
+                         "512 x 512 x 128 workload")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--repeats", type=int, default=10)
     ap.add_argument("--flow", choices=["channel", "open"], default="channel",
@@ -454,6 +504,7 @@ def main(argv=None):
     ap.add_argument("--rounds", type=int, default=200)
     ap.add_argument("--ams-n", type=int, default=256)
     ap.add_argument("--ams-z", type=float, default=5.0, help="AMS level in window standard deviations")
+    ap.add_argument("--ams-scores", default="plain,learned", help="which AMS scores to run")
     ap.add_argument("--direct-steps", type=int, default=200_000)
     ap.add_argument("--eps", type=float, default=0.002)
     ap.add_argument("--clone-tc", type=float, default=1.0, help="GKTL cloning period in correlation times")
@@ -478,6 +529,20 @@ def main(argv=None):
         open_channel_stats(OpenFlow(), args.n, args.open_burn, args.open_steps, out=args.out)
     if args.which == "score":  # the learned score's training and its prediction against the plain score
         train_score(flow, args.ams_n, args.rounds, 512, out=args.out)
+    if args.which == "cfg3":
+        fl = gktl_flow()
+        if args.burn is not None:
+            fl.burn = args.burn
+        gktl_and_direct(fl, 256, args.repeats, ks=[float(k) for k in args.ks.split(",")], out=args.out,
+                        direct_steps=args.direct_steps, eps=args.eps, n_src=256,
+                        fixed=dict(tau=256, window=2048, t_a=6144, dt=1.0 / 512.0),
+                        zs=(1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0))
+    if args.which == "cfg4":
+        fl = ams_flow()
+        if args.burn is not None:
+            fl.burn = args.burn
+        ams_compare(fl, 512, args.repeats, out=args.out, rounds=args.rounds, eps=args.eps, z=args.ams_z,
+                    direct_steps=args.direct_steps, scores=tuple(args.ams_scores.split(",")))
 
 
 if __name__ == "__main__":

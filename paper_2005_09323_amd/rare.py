@@ -207,26 +207,48 @@ class AmsRunner:
 
     # -- stepping ----------------------------------------------------------
     def _features(self, members: Sequence[int], times: np.ndarray) -> None:
+        """Network scores of `members` at their current times: one feature pass and one forward
+        pass over the ensemble, one scatter into the score grid."""
         if self.net is None:
             return
         f = self.ens.features(0, self.ens.n, **self.fargs)
-        y = self.net.forward(f)
-        for m in members:
-            self.ghat[m, times[m] // self.stride - 1] = y[m]
+        step = self.net.max_batch
+        y = torch.cat([self.net.forward(f[b:b + step]) for b in range(0, f.shape[0], step)])
+        idx = torch.as_tensor(list(members), dtype=torch.long, device=self.ghat.device)
+        col = torch.as_tensor(times[list(members)] // self.stride - 1, dtype=torch.long, device=self.ghat.device)
+        self.ghat[idx, col] = y[idx]
 
     def _advance(self, members: Sequence[int], perturb_at: dict, period: int) -> int:
-        """Run `members` from their times to t_a on the stride grid; returns member-steps."""
+        """Run `members` from their times to t_a on the stride grid; returns member-steps.
+
+        The active members step together up to the next time at which one of them has something
+        to do: a checkpoint, its branching perturbation, the end of its trajectory, and, with a
+        learned score, every point of the score grid (the network's score needs the state)."""
         ens = self.ens
         n = ens.n
         active = [m for m in members if self.time[m] < self.t_a]
         steps = 0
+        mask_now = None
         while active:
             mask = np.zeros(n, dtype=np.int32)
             mask[active] = 1
-            ens.set_active(mask.tolist())
-            ens.step(self.stride)
-            steps += self.stride * len(active)
-            self.time[active] += self.stride
+            if mask_now is None or not np.array_equal(mask, mask_now):
+                ens.set_active(mask.tolist())
+                mask_now = mask
+            if self.net is not None:
+                delta = self.stride
+            else:
+                delta = self.t_a
+                for m in active:  # no member may step past its own next event
+                    t = int(self.time[m])
+                    nxt = min((t // self.ckpt + 1) * self.ckpt, self.t_a)
+                    tb = perturb_at.get(m, -1)
+                    if tb > t:
+                        nxt = min(nxt, tb)
+                    delta = min(delta, nxt - t)
+            ens.step(delta)
+            steps += delta * len(active)
+            self.time[active] += delta
             self._features(active, self.time)  # before any perturbation: the child still equals its parent
             pert = [m for m in active if perturb_at.get(m, -1) == self.time[m]]
             if pert and self.eps != 0.0:
@@ -270,8 +292,8 @@ class AmsRunner:
             score = self.score_series()
             sel = ams_score_kill_branch(score, n_kill, self.key, it)
             maxima = sel["maxima"].double().cpu().numpy()
-            if maxima.min() >= threshold:
-                break
+            if maxima.min() >= threshold or sel["level"] >= threshold:
+                break  # every trajectory reached the target, or the level did (killing would discard hits)
             if sel["parents"].numel() and int(sel["parents"][0].item()) < 0:
                 res.extinct = True
                 break

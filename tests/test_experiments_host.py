@@ -37,3 +37,15 @@ def test_autocorrelation_first_zero_of_a_sine():
     acf = _autocorrelation(d)
     assert abs(acf[0] - 1) < 1e-12
     assert abs(_first_zero(acf) - P / 4) <= 1
+
+
+def test_return_time_flows_follow_their_workloads():
+    """The GKTL and AMS experiment flows keep their workloads' lattice, square and tau (only the
+    force density and the collision are the experiments' own, for stability)."""
+    import workloads
+    from paper_2005_09323_amd import experiments
+    for flow, wl in ((experiments.gktl_flow(), workloads.gktl_ensemble()),
+                     (experiments.ams_flow(), workloads.ams_ensemble())):
+        m = wl.members[0]
+        assert (flow.nx, flow.ny, flow.tau, tuple(flow.square)) == (m.nx, m.ny, m.tau, tuple(m.square))
+        assert flow.collision == "central" and callable(flow.start) and callable(flow.ensemble)

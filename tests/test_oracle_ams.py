@@ -156,3 +156,38 @@ def test_learned_score_ams_unbiased_on_ou_where_the_hard_clamp_ties():
     mean, se = np.mean(est), np.std(est, ddof=1) / math.sqrt(len(est))
     assert abs(mean - brute) < 4 * se + 0.004, (mean, brute, se)
     assert np.mean(k_hard) > 2.0 and max(k_hard) >= 8, (np.mean(k_hard), max(k_hard))
+
+
+def test_ams_stops_when_the_level_reaches_the_threshold():
+    """n_kill = 4 on OU with the learned-score map (which stays at the threshold once the event
+    has happened): AMS stops once the 4th lowest maximum reaches the threshold; the estimate
+    matches brute force and no run goes extinct.  Where a run stops that way, one more
+    selection would have discarded every trajectory (all maxima at or below a level equal to the
+    threshold), which is what happened before the stop existed."""
+    dt, n_steps, a, width, n_kill = 0.02, 100, 1.2, 0.1, 4
+    rng = np.random.default_rng(1)
+    brute = (ou.paths(ou.stationary(200_000, rng), n_steps, dt, rng).max(axis=1) >= a).mean()
+
+    def score(p):
+        return ams.learned_score(p + 0.3, p, a, width)
+
+    def make_resim(rng):
+        def resim(parent, tb, slot, it):
+            tail = ou.paths(np.array([parent[tb]]), n_steps - tb - 1, dt, rng)[0]
+            return np.concatenate([parent[:tb + 1], tail])
+        return resim
+
+    est, by_level = [], 0
+    for rep in range(80):
+        rng = np.random.default_rng(7000 + rep)
+        paths = ou.paths(ou.stationary(16, rng), n_steps, dt, rng)
+        res = ams.run(paths, make_resim(rng), n_kill=n_kill, key=rep, max_iter=400, threshold=a, score=score)
+        assert not res["extinct"]
+        q = ams.clean_maxima(res["scores"])
+        est.append(ams.estimate(res["k_history"], 16, q, np.array([a]))[0])
+        if q.min() < a:  # stopped by the level, not because every trajectory reached the event
+            by_level += 1
+            assert ams.kill_branch(res["scores"], n_kill, rep, len(res["k_history"])).extinct
+    mean, se = np.mean(est), np.std(est, ddof=1) / math.sqrt(len(est))
+    assert abs(mean - brute) < 4 * se + 0.004, (mean, brute, se)
+    assert by_level >= 20, by_level
