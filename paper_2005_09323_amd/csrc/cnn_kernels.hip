@@ -6,18 +6,27 @@
 // to one number: three 3x3 convolutions with 32 channels (zero padding,
 // ReLU), a global average and a linear read-out.
 //
-// Every convolution is an implicit GEMM on v_mfma_f32_16x16x16_bf16: BF16
-// operands rounded to nearest-even from FP32, FP32 accumulation.  One
-// workgroup (4 waves) owns one image; activations live in LDS as padded
-// 18 x 18 x C tiles (channel fastest), weights as [K][32] with
-// K = (tap, input channel), staged in BF16 once per call.  Weight gradients
-// are written per image and summed in a fixed order afterwards, so every
-// result is deterministic.
+// Every convolution is an implicit GEMM on the BF16 matrix cores: operands
+// rounded to nearest-even from FP32, FP32 accumulation.  Forward: one wave
+// owns one image and needs no barrier; the layer's weights sit in registers
+// as v_mfma_f32_16x16x32_bf16 A fragments (output channels x (tap, input
+// channel)), the activations in the wave's LDS tile (16 x 16 pixels, 40
+// BF16 per pixel: 32 channels and a pad that spreads sixteen consecutive
+// pixels' 16-byte reads over distinct banks), and each output row is
+// written back into the tile two rows after it was computed, when no tap
+// of a later row reads its input any more.  The first layer (3 channels)
+// uses v_mfma_f32_16x16x16_bf16 with four channel slots per tap.  Backward:
+// one workgroup (4 waves) per image on v_mfma_f32_16x16x16_bf16 with padded
+// 18 x 18 x C tiles and [K][32] weight tables, K = (tap, input channel).
+// Weights are staged in BF16 once per call.  Weight gradients are written
+// per image and summed in a fixed order afterwards, so every result is
+// deterministic.
 #include "cnn_kernels.hpp"
 
 namespace lbm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NC = 32;   // channels of every hidden layer
@@ -41,28 +50,49 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 // Lane layout of the 16x16x16 BF16 MFMA: lane l supplies A[l % 16][4 (l / 16) + j]
-// and B[4 (l / 16) + j][l % 16] (j = 0..3) and receives D[4 (l / 16) + j][l % 16].
+// and B[4 (l / 16) + j][l % 16] (j = 0..3) and receives D[4 (l / 16) + j][l % 16];
+// of the 16x16x32 one: A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
+// (j = 0..7), the same D.
 
 // The three layers' tables wt[k][o] (k = tap * cin + c, zero rows up to kp)
 // in BF16, once per call: layer 1 at 0 (kp = 32), layer 2 at 32 * 32, layer 3
-// at (32 + 288) * 32.
+// at (32 + 288) * 32; then the A fragments of the forward kernel (o = 16 tile
+// + lane % 16; layer 1: tap = 4 k-step + lane / 16, channel slot j (slot 3
+// and taps past 8 zero); layers 2 and 3: input channel 8 (lane / 16) + j).
 __global__ __launch_bounds__(256) void cnn_stage_weights_kernel(const float* __restrict__ params,
                                                                 unsigned short* __restrict__ wt) {
     const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (e >= CNN_WT_ELEMS) return;
-    int layer, r;
-    if (e < 32 * NC) { layer = 0; r = e; }
-    else if (e < (32 + 288) * NC) { layer = 1; r = e - 32 * NC; }
-    else { layer = 2; r = e - (32 + 288) * NC; }
-    const int cin = layer == 0 ? 3 : NC;
-    const float* w = params + (layer == 0 ? CNN_OFF_W1 : (layer == 1 ? CNN_OFF_W2 : CNN_OFF_W3));
-    const int k = r / NC, o = r - k * NC;
     float v = 0.0f;
-    if (k < 9 * cin) {
-        const int tap = k / cin, c = k - tap * cin;
-        v = w[(o * cin + c) * 9 + tap];
+    if (e < CNN_TAB_ELEMS) {
+        int layer, r;
+        if (e < 32 * NC) { layer = 0; r = e; }
+        else if (e < (32 + 288) * NC) { layer = 1; r = e - 32 * NC; }
+        else { layer = 2; r = e - (32 + 288) * NC; }
+        const int cin = layer == 0 ? 3 : NC;
+        const float* w = params + (layer == 0 ? CNN_OFF_W1 : (layer == 1 ? CNN_OFF_W2 : CNN_OFF_W3));
+        const int k = r / NC, o = r - k * NC;
+        if (k < 9 * cin) {
+            const int tap = k / cin, c = k - tap * cin;
+            v = w[(o * cin + c) * 9 + tap];
+        }
+    } else if (e < CNN_FRAG_OFF + CNN_FRAG1_ELEMS) {
+        const int r = e - CNN_FRAG_OFF;
+        const int j = r & 3, lane = (r >> 2) & 63, mt = (r >> 8) & 1, ks = r >> 9;
+        const int o = 16 * mt + (lane & 15), tap = 4 * ks + (lane >> 4);
+        if (tap < 9 && j < 3) v = params[CNN_OFF_W1 + (o * 3 + j) * 9 + tap];
+    } else {
+        const int r0 = e - CNN_FRAG_OFF - CNN_FRAG1_ELEMS;
+        const int layer = r0 >= CNN_FRAG23_ELEMS ? 2 : 1;
+        const int r = r0 - (layer - 1) * CNN_FRAG23_ELEMS;
+        const int j = r & 7, lane = (r >> 3) & 63, mt = (r >> 9) & 1, tap = r >> 10;
+        const int o = 16 * mt + (lane & 15), c = 8 * (lane >> 4) + j;
+        v = params[(layer == 1 ? CNN_OFF_W2 : CNN_OFF_W3) + (o * NC + c) * 9 + tap];
     }
     wt[e] = f2bf(v);
 }
@@ -78,52 +108,6 @@ __device__ void copy_weights(const unsigned short* __restrict__ src, int kp, uns
 __device__ void zero_lds(unsigned short* p, int n) {
     uint4* p4 = (uint4*)p;
     for (int e = (int)threadIdx.x; e < n / 8; e += (int)blockDim.x) p4[e] = uint4{0u, 0u, 0u, 0u};
-}
-
-// acc[mt][nt] += conv of the padded input: output pixel (y = 4 wave + mt,
-// x = 4 (l/16) + j), channel o = 16 nt + l % 16.
-template <int CIN, int CSTRIDE>
-__device__ void conv_fwd(const unsigned short* in, const unsigned short* wt, f32x4 acc[4][2], int wave, int lane) {
-    constexpr int K = 9 * CIN;
-    constexpr int KP = (K + 15) / 16 * 16;
-    const int col = lane & 15, kq = (lane >> 4) * 4;
-    for (int ks = 0; ks < KP / 16; ++ks) {
-        bf16x4 bfr[2];
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bfr[nt][j] = (short)wt[(ks * 16 + kq + j) * WS + nt * 16 + col];
-        int tap[4], ch[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = ks * 16 + kq + j;
-            tap[j] = k < K ? k / CIN : -1;
-            ch[j] = k < K ? k - (k / CIN) * CIN : 0;
-        }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int y = wave * 4 + mt;
-            bf16x4 afr;
-            if constexpr (CIN % 16 == 0) {
-                // the 16 k of a step share one tap and the lane's 4 are consecutive
-                // channels: one 8-byte LDS read
-                const int tp = (ks * 16) / CIN, dy = tp / 3, dx = tp - 3 * (tp / 3);
-                afr = *(const bf16x4*)(in + ((y + dy) * PADW + (col + dx)) * CSTRIDE + ch[0]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    short v = 0;
-                    if (tap[j] >= 0) {
-                        const int dy = tap[j] / 3, dx = tap[j] - 3 * (tap[j] / 3);
-                        v = (short)in[((y + dy) * PADW + (col + dx)) * CSTRIDE + ch[j]];
-                    }
-                    afr[j] = v;
-                }
-            }
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(afr, bfr[nt], acc[mt][nt]);
-        }
-    }
 }
 
 // Data gradient of a 32 -> 32 convolution: dX[p][c] = sum_{tap, o} dZ[p - tap + 1][o] W[o][c][tap],
@@ -224,26 +208,6 @@ __device__ void load_act(const unsigned short* __restrict__ act, unsigned short*
     }
 }
 
-// Bias, ReLU and store of a layer output (accumulator layout) into a padded
-// tile and, if act is given, into the saved activation.
-__device__ void relu_store(f32x4 acc[4][2], const float* __restrict__ bias, unsigned short* tile,
-                           unsigned short* __restrict__ act, float vals[4][2][4], int wave, int lane) {
-    const int col = lane & 15, kq = (lane >> 4) * 4;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int y = wave * 4 + mt, x = kq + j, o = nt * 16 + col;
-                const float a = fmaxf(acc[mt][nt][j] + bias[o], 0.0f);
-                vals[mt][nt][j] = a;
-                const unsigned short b = f2bf(a);
-                if (tile) tile[((y + 1) * PADW + (x + 1)) * TS + o] = b;
-                if (act) act[(y * 16 + x) * NC + o] = b;
-            }
-}
-
 __device__ void zero_acc(f32x4 acc[4][2]) {
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -251,52 +215,183 @@ __device__ void zero_acc(f32x4 acc[4][2]) {
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
-__global__ __launch_bounds__(256) void cnn_forward_kernel(CnnArgs a) {
-    __shared__ uint4 buf0_4[PAD_ELEMS / 8];  // 16-byte aligned for the vector LDS reads
-    __shared__ uint4 buf1_4[PAD_ELEMS / 8];
-    unsigned short* const buf0 = (unsigned short*)buf0_4;
-    unsigned short* const buf1 = (unsigned short*)buf1_4;
-    __shared__ uint4 wt4[9 * NC * WS / 8];
-    unsigned short* const wt = (unsigned short*)wt4;
-    __shared__ float red[16 * NC];
-    __shared__ float gsum[NC];
+// ---- forward: one wave per image ------------------------------------------
+
+constexpr int TB = 40;  // BF16 elements per pixel of the forward tile (80 bytes)
+
+// One bf16x8 from 16 bytes of LDS.
+__device__ __forceinline__ bf16x8 lds_b8(const unsigned short* p) {
+    return __builtin_bit_cast(bf16x8, *(const uint4*)p);
+}
+
+// Bias, ReLU and BF16 of the lane's output values of one row (two output
+// tiles: channels 16 mt + 4 (lane / 16) + j of pixel lane % 16); into the tile
+// (8-byte writes) and the saved activation.
+__device__ __forceinline__ void fwd_row_out(const f32x4 acc[2], const float bias[2][4], int y, int col, int g,
+                                            unsigned short* tile, unsigned short* __restrict__ act, float cs[2][4]) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        ushort4 o;
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = fmaxf(acc[mt][j] + bias[mt][j], 0.0f);
+        o.x = f2bf(v[0]);
+        o.y = f2bf(v[1]);
+        o.z = f2bf(v[2]);
+        o.w = f2bf(v[3]);
+        const int c0 = 16 * mt + 4 * g;
+        if (tile) *(ushort4*)(tile + (y * 16 + col) * TB + c0) = o;
+        if (act) *(ushort4*)(act + (y * 16 + col) * NC + c0) = o;
+        if (cs) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cs[mt][j] += v[j];
+        }
+    }
+}
+
+// One 32 -> 32 layer of the wave's image, in place in its tile: rows in pairs;
+// a pair's outputs are written once the next pair has been computed (the next
+// pair's taps read the last row of this pair's inputs; no later pair reads
+// them).  A wave's LDS accesses complete in program order, so the writes
+// cannot overtake the reads before them.  Taps reaching past the top or bottom row are
+// skipped (wave-uniform), past the left or right column read zero.  The last
+// layer keeps its outputs out of the tile and sums them per channel (cs).
+__device__ __forceinline__ void fwd_layer32(unsigned short* tile, const unsigned short* __restrict__ frag,
+                                            const float* __restrict__ bias_p, unsigned short* __restrict__ act,
+                                            float cs[2][4], int lane) {
+    const int col = lane & 15, g = lane >> 4;
+    bf16x8 w[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+            w[t][mt] = __builtin_bit_cast(bf16x8, *(const uint4*)(frag + ((t * 2 + mt) * 64 + lane) * 8));
+    float bias[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias[mt][j] = bias_p[16 * mt + 4 * g + j];
+    unsigned short* const out_tile = cs ? nullptr : tile;
+    f32x4 prev[2][2];
+    for (int yp = 0; yp < 8; ++yp) {
+        const int y0 = 2 * yp;
+        f32x4 cur[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) cur[r][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const int px = col + dx;
+            const bool inside = px >= 0 && px < 16;
+            const int pxc = inside ? px : col;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int ys = y0 + r + dy;
+                if (ys < 0 || ys > 15) continue;  // wave-uniform
+                bf16x8 v = lds_b8(tile + (ys * 16 + pxc) * TB + 8 * g);
+                if (!inside) v = bf16x8{};
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) cur[r][mt] = mfma32(w[t][mt], v, cur[r][mt]);
+            }
+        }
+        if (yp > 0) {  // the previous pair: this pair's taps have read its inputs, later pairs' do not
+            fwd_row_out(prev[0], bias, y0 - 2, col, g, out_tile, act, cs);
+            fwd_row_out(prev[1], bias, y0 - 1, col, g, out_tile, act, cs);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) prev[r][mt] = cur[r][mt];
+    }
+    fwd_row_out(prev[0], bias, 14, col, g, out_tile, act, cs);
+    fwd_row_out(prev[1], bias, 15, col, g, out_tile, act, cs);
+}
+
+__global__ __launch_bounds__(64) void cnn_forward_kernel(CnnArgs a) {
+    __shared__ uint4 tile4[256 * TB / 8];  // the activation tile: 16 x 16 pixels x TB
+    __shared__ uint2 in2[256];             // the input picture: 16 x 16 pixels x 4 channel slots
+    __shared__ float gs[NC];
+    unsigned short* const tile = (unsigned short*)tile4;
     const int b = (int)blockIdx.x;
-    const int lane = (int)(threadIdx.x & 63);
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)threadIdx.x, col = lane & 15, g = lane >> 4;
     const float* p = a.params;
-    unsigned short* act = a.act ? a.act + (long long)b * 3 * 256 * NC : nullptr;
-    f32x4 acc[4][2];
-    float vals[4][2][4];
-
-    load_input(a.x + (long long)b * 3 * 256, buf0);
-    copy_weights(a.wt, 32, wt);
-    zero_lds(buf1, PAD_ELEMS);
+    unsigned short* const act = a.act ? a.act + (long long)b * 3 * 256 * NC : nullptr;
+    // the picture in BF16, pixel-major, channel slot 3 zero
+    const float* x = a.x + (long long)b * 3 * 256;
+    for (int q = lane; q < 256; q += 64) {
+        ushort4 v;
+        v.x = f2bf(x[q]);
+        v.y = f2bf(x[256 + q]);
+        v.z = f2bf(x[512 + q]);
+        v.w = 0;
+        in2[q] = __builtin_bit_cast(uint2, v);
+    }
     __syncthreads();
-    zero_acc(acc);
-    conv_fwd<3, 4>(buf0, wt, acc, wave, lane);
-    relu_store(acc, p + CNN_OFF_B1, buf1, act, vals, wave, lane);
+    // layer 1 (3 -> 32): k = (tap, channel slot), tap = 4 k-step + lane / 16
+    {
+        const unsigned short* f1 = a.wt + CNN_FRAG_OFF;
+        bf16x4 w1[3][2];
+#pragma unroll
+        for (int ks = 0; ks < 3; ++ks)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+                w1[ks][mt] = __builtin_bit_cast(bf16x4, *(const uint2*)(f1 + ((ks * 2 + mt) * 64 + lane) * 4));
+        float bias[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bias[mt][j] = p[CNN_OFF_B1 + 16 * mt + 4 * g + j];
+        for (int y0 = 0; y0 < 16; y0 += 2) {
+            f32x4 cur[2][2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) cur[r][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 3; ++ks) {
+                const int tap = 4 * ks + g;
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const int px = col + dx;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int ys = y0 + r + dy;
+                    const bool ok = tap < 9 && px >= 0 && px < 16 && ys >= 0 && ys < 16;
+                    const uint2 raw = in2[ok ? ys * 16 + px : 0];
+                    const bf16x4 v = ok ? __builtin_bit_cast(bf16x4, raw) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) cur[r][mt] = mfma16(w1[ks][mt], v, cur[r][mt]);
+                }
+            }
+            fwd_row_out(cur[0], bias, y0, col, g, tile, act, nullptr);
+            fwd_row_out(cur[1], bias, y0 + 1, col, g, tile, act, nullptr);
+        }
+    }
     __syncthreads();
-
-    copy_weights(a.wt + 32 * NC, 9 * NC, wt);
-    zero_lds(buf0, PAD_ELEMS);
+    fwd_layer32(tile, a.wt + CNN_FRAG_OFF + CNN_FRAG1_ELEMS, p + CNN_OFF_B2, act ? act + 256 * NC : nullptr,
+                nullptr, lane);
     __syncthreads();
-    zero_acc(acc);
-    conv_fwd<NC, TS>(buf1, wt, acc, wave, lane);
-    relu_store(acc, p + CNN_OFF_B2, buf0, act ? act + 256 * NC : nullptr, vals, wave, lane);
+    float cs[2][4] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+    fwd_layer32(tile, a.wt + CNN_FRAG_OFF + CNN_FRAG1_ELEMS + CNN_FRAG23_ELEMS, p + CNN_OFF_B3,
+                act ? act + 2 * 256 * NC : nullptr, cs, lane);
+    // per-channel sums over the 16 pixel columns (the lanes of one row of 16), fixed order
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = cs[mt][j];
+#pragma unroll
+            for (int m = 8; m > 0; m >>= 1) v += __shfl_xor(v, m, 16);
+            if (col == 0) gs[16 * mt + 4 * g + j] = v;
+        }
     __syncthreads();
-
-    copy_weights(a.wt + (32 + 288) * NC, 9 * NC, wt);
-    __syncthreads();
-    zero_acc(acc);
-    conv_fwd<NC, TS>(buf0, wt, acc, wave, lane);
-    relu_store(acc, p + CNN_OFF_B3, nullptr, act ? act + 2 * 256 * NC : nullptr, vals, wave, lane);
-    channel_sum(vals, red, gsum, wave, lane);
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         float y = p[CNN_OFF_B4];
         for (int o = 0; o < NC; ++o) {
-            const float g = gsum[o] * (1.0f / 256.0f);
-            if (a.gap) a.gap[(long long)b * NC + o] = g;
-            y += g * p[CNN_OFF_W4 + o];
+            const float gm = gs[o] * (1.0f / 256.0f);
+            if (a.gap) a.gap[(long long)b * NC + o] = gm;
+            y += gm * p[CNN_OFF_W4 + o];
         }
         a.y[b] = y;
     }
@@ -515,7 +610,7 @@ hipError_t launch_cnn_forward(const CnnArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(cnn_stage_weights_kernel, dim3((CNN_WT_ELEMS + 255) / 256), dim3(256), 0, st, a.params, a.wt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cnn_forward_kernel, dim3(a.batch), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(cnn_forward_kernel, dim3(a.batch), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_cnn_backward(const CnnArgs& a, hipStream_t st) {

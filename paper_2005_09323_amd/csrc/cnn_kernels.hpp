@@ -22,10 +22,17 @@ struct CnnArgs {
     float* partial;       // [batch][CNN_N_PARAMS]
     float* grads;         // [CNN_N_PARAMS]
     float* loss;          // [1] or null
-    unsigned short* wt;   // BF16 weight tables [layer][kp][32], kp = 32, 288, 288 (staged once per call)
+    unsigned short* wt;   // BF16 weight tables [layer][kp][32], kp = 32, 288, 288, then the A fragments (staged once per call)
 };
 
-constexpr int CNN_WT_ELEMS = (32 + 288 + 288) * 32;  // the three staged weight tables
+constexpr int CNN_TAB_ELEMS = (32 + 288 + 288) * 32;  // the three staged weight tables [k][o]
+// The weights again as matrix-core A fragments, one 16-byte (8 x BF16) or
+// 8-byte (layer 1) piece per lane: layer 1 [k-step 3][o tile 2][lane 64][4],
+// layers 2 and 3 [tap 9][o tile 2][lane 64][8].
+constexpr int CNN_FRAG1_ELEMS = 3 * 2 * 64 * 4;
+constexpr int CNN_FRAG23_ELEMS = 9 * 2 * 64 * 8;
+constexpr int CNN_FRAG_OFF = CNN_TAB_ELEMS;
+constexpr int CNN_WT_ELEMS = CNN_TAB_ELEMS + CNN_FRAG1_ELEMS + 2 * CNN_FRAG23_ELEMS;  // everything staged per call
 
 struct AdamArgs {
     float* params;
