@@ -461,7 +461,11 @@ int ams_learned_score(const float* ghat_dev, const float* ft_dev, int64_t count,
  */
 int32_t score_net_params(void);
 
-/* Device workspace (256-byte aligned) score_net_forward / score_net_grad need for a batch. */
+/*
+ * Device workspace (256-byte aligned) score_net_forward / score_net_grad need
+ * for a batch; it serves every smaller batch too (the size never decreases
+ * with the batch).
+ */
 size_t score_net_workspace_bytes(int32_t batch);
 
 /*
@@ -483,10 +487,11 @@ int score_net_forward(const float* params_dev, const float* x_dev, int32_t batch
  * Gradient of the mean squared error (1/B) sum_b (y_b - label_b)^2 with
  * respect to every parameter (device float[score_net_params()]), and the loss
  * into loss_dev (device float, may be NULL).  Deterministic for a given batch
- * size: per-image contributions are added in image order within chunks of c
- * images, c the smallest power of two from 8 to 256 with c * c >= batch (16
- * at a batch of 256), then the chunk sums in chunk order; the loss by a
- * fixed-order tree.
+ * size: the images are taken k at a time (k = batch / 2048 clamped to 1..8),
+ * each group's contributions added in image order into one row; the rows are
+ * added in order within chunks of c rows, c the smallest power of two from 8
+ * to 256 with c * c >= the number of rows (16 at a batch of 256), then the
+ * chunk sums in chunk order; the loss by a fixed-order tree.
  */
 int score_net_grad(const float* params_dev, const float* x_dev, const float* labels_dev, int32_t batch,
                    float* grads_dev, float* loss_dev, void* workspace, size_t workspace_bytes, void* hip_stream);

@@ -27,7 +27,7 @@ constexpr WsLayout layout(int batch) {
     w.y = off;
     off += align256((size_t)batch * sizeof(float));
     w.partial = off;
-    off += align256((size_t)cnn_partial_rows(batch) * CNN_PART_STRIDE * sizeof(float));
+    off += align256((size_t)cnn_partial_rows_cap(batch) * CNN_PART_STRIDE * sizeof(float));
     w.total = off;
     return w;
 }

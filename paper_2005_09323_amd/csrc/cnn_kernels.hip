@@ -621,7 +621,7 @@ __global__ __launch_bounds__(256) void cnn_reduce_chunks_kernel(CnnArgs a) {
     const int k0 = (int)blockIdx.y * rc, k1 = min(k0 + rc, rows);
     float4 tot = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float* src = a.partial + (long long)k0 * CNN_PART_STRIDE + r4;
-#pragma unroll 4
+#pragma unroll 8
     for (int k = k0; k < k1; ++k, src += CNN_PART_STRIDE) {
         const float4 v = *(const float4*)src;
         tot.x += v.x;
@@ -661,7 +661,9 @@ __global__ __launch_bounds__(256) void cnn_reduce_final_kernel(CnnArgs a) {
     const int dst = canon_index(r);
     if (dst >= 0) {
         float tot = 0.0f;
-        for (int c = 0; c < chunks; ++c) tot += a.partial[(long long)c * rc * CNN_PART_STRIDE + r];
+        const float* src = a.partial + r;
+#pragma unroll 8
+        for (int c = 0; c < chunks; ++c, src += (long long)rc * CNN_PART_STRIDE) tot += *src;  // loads in flight, sums in order
         a.grads[dst] = tot;
     }
     if (blockIdx.x == 0 && a.loss) {  // the whole first workgroup

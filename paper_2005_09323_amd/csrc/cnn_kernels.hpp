@@ -32,6 +32,14 @@ __host__ __device__ constexpr int cnn_images_per_group(int batch) {
 __host__ __device__ constexpr int cnn_partial_rows(int batch) {
     return (batch + cnn_images_per_group(batch) - 1) / cnn_images_per_group(batch);
 }
+// The most rows any batch up to `batch` uses (cnn_partial_rows itself drops
+// where the group size steps up, 4095 -> 2048 at 4096): at most 4095 below a
+// batch of 16384 (one image per group up to 4095, then groups of k up to
+// 2048 (k + 1) - 1 images), ceil(batch / 8) above; the workspace is sized by
+// it so that one serves every smaller batch.
+__host__ __device__ constexpr int cnn_partial_rows_cap(int batch) {
+    return (batch < 4095 ? batch : 4095) > (batch + 7) / 8 ? (batch < 4095 ? batch : 4095) : (batch + 7) / 8;
+}
 
 struct CnnArgs {
     const float* params;

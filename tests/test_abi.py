@@ -26,6 +26,22 @@ def test_state_floats():
     assert lib.lbm_state_floats(None, 0) == 0
 
 
+def test_score_workspace_serves_every_smaller_batch():
+    """The score network's gradient rows depend on how many images a backward
+    workgroup takes (one below a batch of 4096, then up to 8), so their count
+    drops where that number steps up (4095 images: 4095 rows, 4096: 2048);
+    the workspace size must still never decrease with the batch, so that a
+    workspace for a batch serves every smaller one."""
+    lib = native.lib()
+    lib.score_net_workspace_bytes.restype = ctypes.c_size_t
+    prev = 0
+    for b in list(range(1, 9000)) + list(range(9000, 70000, 7)) + [2 ** 20]:
+        n = lib.score_net_workspace_bytes(b)
+        assert n >= prev, b
+        prev = n
+    assert lib.score_net_workspace_bytes(0) == 0
+
+
 def _create(members, pop_floats=10**9, cap=10, a=256, b=512, series=768, accum=1024):
     lib = native.lib()
     ctx = ctypes.c_void_p()

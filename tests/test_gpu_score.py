@@ -113,6 +113,49 @@ def test_gradients_match_oracle(batch):
     assert abs(net.loss.item() / loss_ref - 1) < 1e-2
 
 
+@pytest.mark.parametrize("batch,sub,tol", [(16384, 2048, 1e-5), (4097, 2047, 2e-3)])
+def test_multi_image_workgroups_match_single_image_sub_batches(batch, sub, tol):
+    """From a batch of 4096 on, a backward workgroup takes several images in
+    turn (8 at 16384; 2 at 4097, the last workgroup one) and sums them into one
+    gradient row.  Sub-batches of at most 2047 (2048) images run one image per
+    workgroup, the path pinned to the oracle above, and the batch's mean
+    gradient is their mean gradients weighted by their sizes.  The kernel
+    scales dZ by 1/batch before rounding it to BF16; rounding commutes with a
+    power-of-two scale, so at 16384 = 8 x 2048 the two agree up to FP32
+    summation order (1e-5), while at 4097 = 2047 + 2047 + 3 every BF16
+    rounding of dZ lands differently: the tensors behind it (w1 .. w3) move by
+    the BF16 rounding noise (<= 2e-3; measured 1.7e-4 .. 3.1e-4), the ones
+    computed in FP32 throughout (b3, w4, b4) by <= 1e-5.  The forward pass is
+    per image: bit-identical."""
+    p = workloads.cnn_params(31)
+    x, lab = workloads.cnn_batch(batch, 32)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    lt = torch.from_numpy(lab.astype(np.float32)).cuda()
+    net = _net(_flat(p), batch)
+    g = net.grad(xt, lt).cpu().numpy().astype(np.float64)
+    loss = net.loss.item()
+    y = net.forward(xt).cpu()
+    subnet = _net(_flat(p), sub)
+    ref = np.zeros_like(g)
+    loss_ref = 0.0
+    ys = []
+    for s0 in range(0, batch, sub):
+        s1 = min(s0 + sub, batch)
+        ref += (s1 - s0) / batch * subnet.grad(xt[s0:s1].contiguous(), lt[s0:s1].contiguous()).cpu().numpy()
+        loss_ref += (s1 - s0) / batch * subnet.loss.item()
+        ys.append(subnet.forward(xt[s0:s1].contiguous()).cpu())
+    assert torch.equal(y, torch.cat(ys))
+    gg, rr = _unflat(g), _unflat(ref)
+    errs = {k: _rel_l2(gg[k], rr[k]) for k in NAMES}
+    print(f"batch {batch} gradient vs sub-batches of {sub}, relative L2 per tensor:",
+          {k: f"{v:.1e}" for k, v in errs.items()})
+    for k in NAMES:
+        assert errs[k] <= (1e-5 if k in ("b3", "w4", "b4") else tol), (k, errs[k])
+    assert abs(loss / loss_ref - 1) < 1e-5
+    g2 = net.grad(xt, lt).cpu().numpy().astype(np.float64)
+    assert np.array_equal(g, g2)  # deterministic
+
+
 def test_zero_network_gives_bias_and_deterministic():
     p = {k: np.zeros_like(v) for k, v in workloads.cnn_params(0).items()}
     p["b4"] = np.array(0.375)
