@@ -153,7 +153,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     // values come from the ghost block, the outlet's are built in phase B)
     const bool own_h = !OPEN || !((lane & 1) ? right_end : left_end);
     const bool sq_cols = m.ss > 0 && base <= m.sx0 + m.ss && base + 255 >= m.sx0 - 1;
-    const bool grid_cols = OPEN && m.bar > 0 && base <= m.gx0 + m.bar && base + 255 >= m.gx0 - 1;
+    // grid bars within the columns any cell of this workgroup pulls from: the
+    // outside cells x0 - 1 and x0 + 256 reach one column further than the
+    // strip's own cells (base - 2 .. base + 257)
+    const bool grid_cols = OPEN && m.bar > 0 && base <= m.gx0 + m.bar + 1 && base + 255 >= m.gx0 - 2;
     const bool sponge = OPEN && base + 255 > m.sp_x0;
     // bit j: column x0 - 1 + j (j = 0..5) holds grid bars
     unsigned gcols = 0;

@@ -319,6 +319,38 @@ def test_open_channel_two_step_bit_identical_to_one_step(collision, outlet_rho):
 
 
 
+@pytest.mark.parametrize("gx0,bar", [(253, 2), (257, 3), (254, 1), (256, 4)])
+def test_two_step_grid_bars_just_beyond_a_strip_seam(gx0, bar):
+    """Bars ending two columns left of the strip seam at x = 256 (253 + 2) or
+    starting two columns right of it (257): only the strips' outside cells
+    (x = 255 and 256, collided by both neighbouring workgroups) pull from
+    them, and the two-step kernel once missed them there (its grid-column
+    range covered the strip's own cells only; the CPU model of its indexing
+    finds that).  Bit-identical to the one-step kernel after 41 steps, both
+    collisions."""
+    from paper_2005_09323_amd.ensemble import Ensemble
+    m = workloads.Member(512, 40, 0.56, 0.0, (400, 15, 6))
+    op = workloads.OpenParams(0.04, gx0, bar, 470, 0.9)
+    for collision in (None, CM_RATES):
+        runs = []
+        for tile in (0, 16):
+            ens = Ensemble([m, m], series_capacity=60)
+            ens.set_tile(tile)
+            if collision is not None:
+                ens.set_collision("central", *collision)
+            ens.set_open_channel(op.u_c, op.grid_x0, op.bar, op.sponge_x0, op.sponge_tau)
+            ens.init(7, 1e-3)
+            ens.step(41)
+            torch.cuda.synchronize()
+            runs.append((ens.drag(0, 42).cpu().numpy(), [ens.state(i).cpu().numpy().copy() for i in range(2)]))
+            ens.close()
+        (d0, s0), (d1, s1) = runs
+        fluid = ~olbm.solid_mask(_channel(m, op))
+        assert np.array_equal(d0, d1), (gx0, bar, collision)
+        for i in range(2):
+            assert np.array_equal(s0[i][:, fluid], s1[i][:, fluid]), (gx0, bar, collision, i)
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_two_step_bounce_back_over_many_geometries(seed):
     """Bounce-back next to solid cells in the two-step kernel, for squares and grids at seeded
