@@ -235,6 +235,18 @@ def legs():
     ens.close()
     del ens
     torch.cuda.empty_cache()
+    # the same batch with its launch shape tuned, and a row range per lattice size
+    ens = Ensemble(wl.members, series_capacity=300)
+    tile = ens.autotune(16)
+    ens.init(wl.seed, wl.noise_amp)
+    ens.step(20)
+    torch.cuda.synchronize()
+    t_tuned = _timed(lambda: ens.step(256)) / 256
+    out["mixed_sizes"]["tuned"] = {"tile": tile, "rows_per_workgroup_per_size": ens.run_rows(),
+                                   "ms_per_step": round(t_tuned, 4), "MLUPS": round(wl.cells / t_tuned / 1e3, 1)}
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
     # launch-bound batches (an AMS branch re-simulates a handful of members): full 64-step chunks
     # replayed from a captured HIP graph against launching every kernel of every chunk
     m = workloads.ams_ensemble().members[0]

@@ -295,14 +295,38 @@ int32_t lbm_tile_count(void);
    the shape in use and the members active now. */
 int lbm_launch_steps(const lbm_ctx* ctx, int32_t* steps);
 /* Time every tile shape on this ensemble (n_steps each, on the context's
-   stream, synchronising it) and keep the fastest.  Writes the chosen id. */
+   stream, synchronising it) and keep the fastest.  Writes the chosen id.  If
+   that shape makes two steps per launch and the ensemble has several runs of
+   lattice shapes (an uneven batch), each run's row range (whole strips, 128,
+   64 or 32 rows per workgroup) is then tuned on its own, one run at a time,
+   keeping a choice only where the whole ensemble's step is at least 1 %
+   faster; lbm_get_run_rows reads the result.  Earlier lbm_set_run_rows
+   choices are discarded. */
 int lbm_autotune(lbm_ctx* ctx, int32_t n_steps, int32_t* best_tile);
+
+/* Runs of consecutive members with one lattice shape: the ensemble's
+   segments, each with its own row range in two-step launches. */
+int lbm_run_count(const lbm_ctx* ctx, int32_t* n_runs);
+/* Rows per workgroup of each run in two-step launches: rows[r] = -1 as the
+   tile shape says (its own policy), 0 whole strips of 256 columns, else row
+   ranges of rows[r] rows (a range of ny or more is a whole strip).  n_runs
+   must be lbm_run_count's, or 0 (rows may then be NULL) to drop every
+   choice.  Results are bit-identical whatever the ranges (each range
+   collides the rows beside it that its second step pulls).  Kept across
+   lbm_set_tile; LBM_EINVAL on a wrong count or a value below -1 (nothing
+   changes). */
+int lbm_set_run_rows(lbm_ctx* ctx, const int32_t* rows, int32_t n_runs);
+/* The rows per workgroup each run uses now (0: whole strips; -1 for every
+   run if the shape in use makes one step per launch): writes n_runs and, if
+   rows is not NULL, max_runs >= n_runs entries. */
+int lbm_get_run_rows(const lbm_ctx* ctx, int32_t* rows, int32_t max_runs, int32_t* n_runs);
 /* lbm_autotune with a persisted table: path is a text file of lines
-   "<key>\t<tile id>", the key naming the runs of lattice shapes, the
-   collision and whether the channels are open.  A line with this context's
-   key sets its shape without timing anything; otherwise the context is tuned
-   and a line appended (the file is created if missing).  LBM_EINVAL if the
-   line cannot be written (the tuned shape is set all the same). */
+   "<key>\t<tile id>[ <rows of run 0>,<rows of run 1>,...]", the key naming
+   the runs of lattice shapes, the collision and whether the channels are
+   open.  A line with this context's key sets its shape (and row ranges)
+   without timing anything; otherwise the context is tuned and a line
+   appended (the file is created if missing).  LBM_EINVAL if the line cannot
+   be written (the tuned shape is set all the same). */
 int lbm_autotune_cached(lbm_ctx* ctx, int32_t n_steps, const char* path, int32_t* best_tile);
 
 /*

@@ -43,12 +43,13 @@ struct RareScratch {
 // What a captured chunk of lbm_step_batch depends on besides device memory:
 // a replay is valid while all of it is unchanged.
 struct ChunkGraphKey {
-    int tile_id, one_tile, two, waves2, model, open, chunk;
+    int tile_id, one_tile, two, waves2, model, open, chunk, table_gen;
     int total_blocks, total_blocks2, compact;
     double mu, inv_sigma_dt;
     const void* ghost;
     bool operator==(const ChunkGraphKey& o) const {
         return tile_id == o.tile_id && one_tile == o.one_tile && two == o.two && waves2 == o.waves2 &&
+               table_gen == o.table_gen &&
                model == o.model && open == o.open && chunk == o.chunk && total_blocks == o.total_blocks &&
                total_blocks2 == o.total_blocks2 && compact == o.compact && mu == o.mu &&
                inv_sigma_dt == o.inv_sigma_dt && ghost == o.ghost;
@@ -96,6 +97,10 @@ struct lbm_ctx {
     int total_blocks = 0;
     lbm::Segment seg[lbm::MAX_SEGMENTS];
     // two-step launches (when the chosen shape has two steps and every member qualifies)
+    // rows per workgroup of each run of equal lattice shapes (its segment of the
+    // two-step table): -1 as the shape says, 0 whole strips, else a row range
+    std::vector<int> run_rows;
+    int table_gen = 0;  // bumped whenever the tables are rebuilt (captured graphs hold them)
     bool two_step = false;
     bool split2 = false;  // some strip of the two-step table is split into row ranges
     int nseg2 = 0;

@@ -138,14 +138,18 @@ static int strip_rows(const lbm_ctx* c, const TileShape& ts) {
 // workgroup per 256-column strip, or per row range of one: Segment::rows).
 static int build_table(lbm_ctx* c, const TileShape& ts, bool strips, Segment* seg, int& nseg, int& total) {
     const int rows = ts.tyt * ts.r;
-    const int split = strips ? strip_rows(c, ts) : 0;
+    const int shape_split = strips ? strip_rows(c, ts) : 0;
     nseg = 0;
     int blocks = 0;
     for (int m = 0; m < c->n; ++m) {
         const auto& d = c->desc[m];
         const bool same = nseg > 0 && c->desc[seg[nseg - 1].member_begin].nx == d.nx &&
                           c->desc[seg[nseg - 1].member_begin].ny == d.ny;
-        const int hseg = split > 0 ? std::min(split, d.ny) : d.ny;  // strips: rows per workgroup
+        // strips: rows per workgroup, the run's own choice if it has one
+        const int run = same ? nseg - 1 : nseg;
+        const int split = strips && run < (int)c->run_rows.size() && c->run_rows[run] >= 0 ? c->run_rows[run]
+                                                                                           : shape_split;
+        const int hseg = split > 0 ? std::min(split, d.ny) : d.ny;
         const int tx = (d.nx + 255) / 256, ty = strips ? (d.ny + hseg - 1) / hseg : (d.ny + rows - 1) / rows;
         if (!same) {
             if (nseg == MAX_SEGMENTS)
@@ -194,6 +198,7 @@ static bool two_step_now(const lbm_ctx* c) {
 // steps with the one-step shape 0, which gives the same results.
 static int build_segments(lbm_ctx* c) {
     const TileShape ts = TILE_SHAPES[c->tile_id];
+    ++c->table_gen;
     c->two_step = false;
     c->one_tile = c->tile_id;
     if (ts.steps == 2) {
@@ -506,7 +511,7 @@ extern "C" int lbm_step_batch(lbm_ctx* c, int32_t n_steps) {
         int launches = 0;
         if (c->graphs && chunk == c->chunk) {
             ChunkGraphKey key{c->tile_id, c->one_tile, two ? 1 : 0, waves2, c->model, c->open ? 1 : 0, chunk,
-                              a.total_blocks, a2.total_blocks, a.active_list ? 1 : 0, c->mu, c->dt / c->sigma,
+                              c->table_gen, a.total_blocks, a2.total_blocks, a.active_list ? 1 : 0, c->mu, c->dt / c->sigma,
                               (const void*)c->d_ghost};
             if (!c->graph_exec || !(key == c->graph_key)) {
                 free_chunk_graph(c);
@@ -707,6 +712,57 @@ extern "C" int lbm_set_tile(lbm_ctx* c, int32_t tile_id) {
     return rc;
 }
 
+// Runs of consecutive members with one lattice shape (the segments of the tables).
+static int count_runs(const lbm_ctx* c) {
+    int runs = 0;
+    for (int m = 0; m < c->n; ++m)
+        if (m == 0 || c->desc[m].nx != c->desc[m - 1].nx || c->desc[m].ny != c->desc[m - 1].ny) ++runs;
+    return runs;
+}
+
+extern "C" int lbm_run_count(const lbm_ctx* c, int32_t* n_runs) {
+    if (!c || !n_runs) return lbm_fail(LBM_EINVAL, "NULL argument");
+    *n_runs = count_runs(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_run_rows(lbm_ctx* c, const int32_t* rows, int32_t n_runs) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (n_runs == 0) {
+        c->run_rows.clear();
+        return build_segments(c);
+    }
+    if (!rows) return lbm_fail(LBM_EINVAL, "NULL rows");
+    if (n_runs != count_runs(c))
+        return lbm_fail(LBM_EINVAL, "%d row ranges for %d runs of lattice shapes", n_runs, count_runs(c));
+    for (int r = 0; r < n_runs; ++r)
+        if (rows[r] < -1) return lbm_fail(LBM_EINVAL, "run %d: rows %d (-1 by the shape, 0 whole strips, >= 1)", r, rows[r]);
+    const std::vector<int> old = c->run_rows;
+    c->run_rows.assign(rows, rows + n_runs);
+    int rc = build_segments(c);
+    if (rc) {
+        c->run_rows = old;
+        build_segments(c);
+    }
+    return rc;
+}
+
+extern "C" int lbm_get_run_rows(const lbm_ctx* c, int32_t* rows, int32_t max_runs, int32_t* n_runs) {
+    if (!c || !n_runs) return lbm_fail(LBM_EINVAL, "NULL argument");
+    *n_runs = c->two_step ? c->nseg2 : count_runs(c);
+    if (rows && max_runs < *n_runs) return lbm_fail(LBM_EINVAL, "room for %d runs, need %d", max_runs, *n_runs);
+    if (rows)
+        for (int s = 0; s < *n_runs; ++s) {
+            if (!c->two_step) {
+                rows[s] = -1;
+                continue;
+            }
+            const int ny = c->desc[c->seg2[s].member_begin].ny;
+            rows[s] = c->seg2[s].rows >= ny ? 0 : c->seg2[s].rows;
+        }
+    return LBM_OK;
+}
+
 extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     if (!c || !best_tile) return lbm_fail(LBM_EINVAL, "NULL argument");
     if (n_steps < 1) return lbm_fail(LBM_EINVAL, "n_steps must be >= 1");
@@ -735,12 +791,15 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     float best_ms = 1e30f;  // per step
     int best = c->tile_id;
     const int pairs = std::max(1, n_steps / 2);
-    for (int t = 0; t < N_TILE_SHAPES; ++t) {
-        c->tile_id = t;
-        if (build_segments(c) != LBM_OK) continue;
+    c->run_rows.clear();  // the shapes first, each with its own row policy
+    // time the current tables with shape t; ms per step, or a negative value
+    // if the shape does not apply
+    auto time_shape = [&](int t, float& ms) -> int {
+        ms = -1.0f;
+        if (build_segments(c) != LBM_OK) return LBM_OK;
         const TileShape ts = TILE_SHAPES[t];
-        if (ts.steps == 2 && !c->two_step) continue;  // it would run shape 0
-        if (ts.adaptive) continue;                    // a policy over shapes 16 and 0, not a shape
+        if (ts.steps == 2 && !c->two_step) return LBM_OK;  // it would run shape 0
+        if (ts.adaptive) return LBM_OK;                    // a policy over shapes 16 and 0, not a shape
         const bool two = ts.steps == 2;
         a.total_blocks = two ? c->total_blocks2 : c->total_blocks;
         a.split = two && c->split2 ? 1 : 0;
@@ -750,7 +809,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         a.slot = 0;
         auto launch = [&](int flip) {
             a.flip = flip;
-            if (c->open) {  // (never two-step)
+            if (c->open) {  // the outlet ghost column the launch's first step pulls
                 g.flip = flip;
                 hipError_t ge = launch_outlet_ghost(g, c->n, c->max_ny, c->stream);
                 if (ge != hipSuccess) return ge;
@@ -767,17 +826,46 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
         }
         hipEventRecord(e1, c->stream);
         hipError_t err = hipEventSynchronize(e1);
-        if (err != hipSuccess) {
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-            return lbm_hip_fail(err, "autotune timing");
-        }
-        float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)(2 * pairs * ts.steps);
-        if (ms < best_ms) {
+        if (err != hipSuccess) return lbm_hip_fail(err, "autotune timing");
+        float t_ms = 0;
+        hipEventElapsedTime(&t_ms, e0, e1);
+        ms = t_ms / (float)(2 * pairs * ts.steps);
+        return LBM_OK;
+    };
+    int rc = LBM_OK;
+    for (int t = 0; t < N_TILE_SHAPES && rc == LBM_OK; ++t) {
+        c->tile_id = t;
+        float ms;
+        rc = time_shape(t, ms);
+        if (rc == LBM_OK && ms >= 0.0f && ms < best_ms) {
             best_ms = ms;
             best = t;
+        }
+    }
+    // Runs of different lattice sizes (an uneven batch): each run's row range
+    // on its own, one run at a time (whole strips, 128, 64 or 32 rows per
+    // workgroup), keeping whatever times best for the whole ensemble.
+    c->tile_id = best;
+    const int runs = count_runs(c);
+    if (rc == LBM_OK && TILE_SHAPES[best].steps == 2 && runs > 1 && build_segments(c) == LBM_OK && c->two_step) {
+        c->run_rows.assign(runs, -1);
+        for (int r = 0; r < runs; ++r) c->run_rows[r] = c->seg2[r].rows >= c->desc[c->seg2[r].member_begin].ny ? 0 : c->seg2[r].rows;
+        rc = time_shape(best, best_ms);  // the reference, timed next to the variants
+        for (int r = 0; r < runs && rc == LBM_OK; ++r) {
+            const int ny = c->desc[c->seg2[r].member_begin].ny;
+            int keep = c->run_rows[r];
+            for (int h : {0, 128, 64, 32}) {
+                if (h == keep || (h > 0 && h >= ny)) continue;
+                c->run_rows[r] = h;
+                float ms;
+                rc = time_shape(best, ms);
+                if (rc != LBM_OK) break;
+                if (ms >= 0.0f && ms < 0.99f * best_ms) {  // a clear gain only
+                    best_ms = ms;
+                    keep = h;
+                }
+            }
+            c->run_rows[r] = keep;
         }
     }
     hipEventDestroy(e0);
@@ -785,7 +873,7 @@ extern "C" int lbm_autotune(lbm_ctx* c, int32_t n_steps, int32_t* best_tile) {
     c->tile_id = best;
     build_segments(c);
     *best_tile = best;
-    return LBM_OK;
+    return rc;
 }
 
 // What a tuned launch shape depends on: the runs of lattice shapes, the
@@ -813,10 +901,23 @@ extern "C" int lbm_autotune_cached(lbm_ctx* c, int32_t n_steps, const char* path
         while (in && std::getline(in, line)) {
             const size_t tab = line.rfind('\t');
             if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
-            const int tile = std::atoi(line.c_str() + tab + 1);
+            // "<tile>" or "<tile> <rows of run 0>,<rows of run 1>,..."
+            std::istringstream val(line.substr(tab + 1));
+            int tile = -1;
+            val >> tile;
+            if (!val && !val.eof()) continue;
             if (tile < 0 || tile >= N_TILE_SHAPES) continue;  // a table from another build: tune again
-            const int rc = lbm_set_tile(c, tile);
+            std::vector<int32_t> rows;
+            std::string list;
+            if (val >> list) {
+                std::istringstream ls(list);
+                std::string item;
+                while (std::getline(ls, item, ',')) rows.push_back((int32_t)std::atoi(item.c_str()));
+            }
+            c->run_rows.clear();
+            int rc = lbm_set_tile(c, tile);
             if (rc) return rc;
+            if (!rows.empty() && (rc = lbm_set_run_rows(c, rows.data(), (int32_t)rows.size())) != LBM_OK) return rc;
             *best_tile = tile;
             return LBM_OK;
         }
@@ -824,7 +925,9 @@ extern "C" int lbm_autotune_cached(lbm_ctx* c, int32_t n_steps, const char* path
     const int rc = lbm_autotune(c, n_steps, best_tile);
     if (rc) return rc;
     std::ofstream out(path, std::ios::app);
-    out << key << '\t' << *best_tile << '\n';
+    out << key << '\t' << *best_tile;
+    for (size_t r = 0; r < c->run_rows.size(); ++r) out << (r ? ',' : ' ') << c->run_rows[r];
+    out << '\n';
     if (!out) return lbm_fail(LBM_EINVAL, "cannot append the tuned shape to %s", path);
     return LBM_OK;
 }

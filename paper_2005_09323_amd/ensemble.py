@@ -166,6 +166,29 @@ class Ensemble:
             native.check(self.lib.lbm_autotune_cached(self._ctx, n_steps, table.encode(), ctypes.byref(best)))
         return best.value
 
+    def run_count(self) -> int:
+        """Runs of consecutive members with one lattice shape."""
+        n = ctypes.c_int32()
+        native.check(self.lib.lbm_run_count(self._ctx, ctypes.byref(n)))
+        return n.value
+
+    def set_run_rows(self, rows: Optional[Sequence[int]]) -> None:
+        """Rows per workgroup of each run in two-step launches (-1: as the shape says, 0: whole
+        strips); None drops every choice."""
+        if rows is None:
+            native.check(self.lib.lbm_set_run_rows(self._ctx, None, 0))
+            return
+        arr = (ctypes.c_int32 * len(rows))(*[int(r) for r in rows])
+        native.check(self.lib.lbm_set_run_rows(self._ctx, arr, len(rows)))
+
+    def run_rows(self) -> list:
+        """The rows per workgroup each run uses now (0: whole strips; -1: one-step launches)."""
+        n = ctypes.c_int32()
+        native.check(self.lib.lbm_get_run_rows(self._ctx, None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_int32 * max(n.value, 1))()
+        native.check(self.lib.lbm_get_run_rows(self._ctx, arr, n.value, ctypes.byref(n)))
+        return [int(arr[i]) for i in range(n.value)]
+
     def set_time(self, t: int) -> None:
         native.check(self.lib.lbm_set_time(self._ctx, t))
 

@@ -69,6 +69,9 @@ _SIG = {
     "lbm_set_graphs": (ctypes.c_int, [_P, _I]),
     "lbm_autotune": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),
     "lbm_autotune_cached": (ctypes.c_int, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_I)]),
+    "lbm_run_count": (ctypes.c_int, [_P, ctypes.POINTER(_I)]),
+    "lbm_set_run_rows": (ctypes.c_int, [_P, _P, _I]),
+    "lbm_get_run_rows": (ctypes.c_int, [_P, _P, _I, ctypes.POINTER(_I)]),
     "gktl_select_clone": (ctypes.c_int, [_P, _D, _U64, _I, _D, _P, _I, _P, _P]),
     "lbm_set_cloning": (ctypes.c_int, [_P, _I]),
     "lbm_perturb": (ctypes.c_int, [_P, _P, _U64, _I, _D, _P, _I]),

@@ -458,6 +458,97 @@ def test_autotune_table_is_reused(tmp_path):
     ens.close()
 
 
+def _uneven():
+    """Three runs of lattice shapes (an uneven batch), squares across strip and row-range seams."""
+    return ([workloads.Member(256, 64, 0.6, 2e-5, (100, 30, 6))] * 3 +
+            [workloads.Member(512, 128, 0.57, 1e-5, (250, 60, 8))] * 2 +
+            [workloads.Member(1024, 96, 0.55, 1e-5, (510, 30, 8))] * 2)
+
+
+def test_run_rows_per_lattice_size_bit_identical():
+    """Row ranges chosen per run of lattice shapes (whole strips, 64, 32 and 16 rows) in two-step
+    launches: every state and drag value equals those of whole strips, for both collisions, over
+    an odd number of steps; get_run_rows reports what each run uses; bad arguments change
+    nothing."""
+    members = _uneven()
+    for collision in (None, (1.0, 1.0, 1.0)):
+        runs = []
+        for rows in (None, [0, 32, 16], [64, 0, 32], [-1, 16, 0]):
+            ens = _ensemble(members, 60)
+            ens.set_tile(16)  # two steps per launch, whole strips
+            if collision is not None:
+                ens.set_collision("central", *collision)
+            assert ens.run_count() == 3
+            if rows is not None:
+                ens.set_run_rows(rows)
+                expect = [0 if r <= 0 or r >= m.ny else r for r, m in zip(rows, (members[0], members[3], members[5]))]
+                assert ens.run_rows() == expect
+            else:
+                assert ens.run_rows() == [0, 0, 0]
+            ens.init(5, 1e-2)
+            ens.step(41)
+            torch.cuda.synchronize()
+            runs.append((ens.drag(0, 42).cpu().numpy(), [ens.state(i).cpu().numpy().copy() for i in (0, 3, 4, 6)]))
+            ens.close()
+        d0, s0 = runs[0]
+        for d, st in runs[1:]:
+            assert np.array_equal(d, d0), collision
+            for i, (a, b) in zip((0, 3, 4, 6), zip(st, s0)):
+                fluid = ~olbm.solid_mask(_channel(members[i]))
+                assert np.array_equal(a[:, fluid], b[:, fluid]), (collision, i)
+    ens = _ensemble(members, 10)
+    ens.set_tile(16)
+    ens.set_run_rows([0, 32, 16])
+    for bad in ([0, 32], [0, 32, 16, 8], [0, -2, 16]):
+        with pytest.raises(RuntimeError):
+            ens.set_run_rows(bad)
+        assert ens.run_rows() == [0, 32, 16]
+    ens.set_run_rows(None)
+    assert ens.run_rows() == [0, 0, 0]
+    ens.set_tile(0)
+    assert ens.run_rows() == [-1, -1, -1]
+    ens.close()
+
+
+def test_autotune_per_lattice_size(tmp_path):
+    """On an uneven batch the tuner keeps one row range per run when it is clearly faster; the
+    table line carries them, a new context reads them back, and the tuned ensemble steps to the
+    same states as the default shape."""
+    from paper_2005_09323_amd.ensemble import Ensemble
+    members = _uneven()
+    table = str(tmp_path / "tiles.txt")
+    ens = Ensemble(members, series_capacity=40)
+    tile = ens.autotune(4, table=table)
+    rows = ens.run_rows()
+    assert len(rows) == 3
+    line = open(table).read().splitlines()[0]
+    key, val = line.split("\t")
+    assert "256x64*3;512x128*2;1024x96*2;" in key
+    if ens.launch_steps() == 2 and ens.run_rows()[0] != -1:
+        assert val.split()[0] == str(tile) and len(val.split()) == 2
+        assert [int(v) for v in val.split()[1].split(",")] == rows
+    ens.init(2, 1e-2)
+    ens.step(33)
+    torch.cuda.synchronize()
+    tuned = [ens.state(i).cpu().numpy().copy() for i in (0, 3, 6)]
+    d_tuned = ens.drag(0, 34).cpu().numpy()
+    ens.close()
+    ens = Ensemble(members, series_capacity=40)
+    assert ens.autotune(4, table=table) == tile
+    assert ens.run_rows() == rows
+    ens.close()
+    ens = Ensemble(members, series_capacity=40)
+    ens.set_tile(0)
+    ens.init(2, 1e-2)
+    ens.step(33)
+    torch.cuda.synchronize()
+    assert np.array_equal(ens.drag(0, 34).cpu().numpy(), d_tuned)
+    for i, a in zip((0, 3, 6), tuned):
+        fluid = ~olbm.solid_mask(_channel(members[i]))
+        assert np.array_equal(ens.state(i).cpu().numpy()[:, fluid], a[:, fluid]), i
+    ens.close()
+
+
 def test_adaptive_shape_cuts_strips_for_a_mid_sized_batch():
     """32 members of 1024 x 256 give 128 whole strips, too few for the device: the default shape
     cuts them into row ranges and still makes two steps per launch; 8 of them active fall back to
