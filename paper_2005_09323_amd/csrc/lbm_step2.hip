@@ -110,6 +110,27 @@ __device__ __forceinline__ void collide_row(const MemberDev& m, f4 p[9], double*
     }
 }
 
+// Halfway bounce-back of the lane's four cells of row y from the solid mask
+// mk of its rows (bit 6 j + dx + 1: column x0 + dx of row y - 1 + j): p[i][k]
+// becomes own[i][k] (the cell's own opposite population) where the cell x0 + k
+// is fluid and the cell it pulls from, x0 + k - c_ix in row y - c_iy, is
+// solid.  For each direction the four cells' tests are one 4-bit field of mk;
+// each choice is a sign-extended bit and a bitwise select, with no branch.
+__device__ __forceinline__ void bounce_select(unsigned mk, int ny, int y, const f4 own[9], f4 p[9]) {
+    const unsigned fluid = ~(mk >> 7) & 0xFu;  // row y, columns x0 .. x0 + 3
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const int ys = y - CY[i];
+        if (ys < 0 || ys >= ny) continue;  // a wall row: the whole row bounces back already
+        const unsigned m = (mk >> (6 * (1 - CY[i]) + 1 - CX[i])) & fluid;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned sel = (unsigned)((int)(m << (31 - k)) >> 31);  // all ones where bit k is set
+            p[i][k] = __uint_as_float((__float_as_uint(own[i][k]) & sel) | (__float_as_uint(p[i][k]) & ~sel));
+        }
+    }
+}
+
 // Velocity ring of the outlet strip: rows y & (VROWS - 1).  Phase B reads
 // rows r - 2 .. r + 2 while phase A writes up to r + 2 + NW - 1, so 16 rows
 // hold every row still needed for NW <= 8.
@@ -273,14 +294,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     ownv[i] = CY[OPP[i]] == 0 ? cur.v[OPP[i]]
                                               : __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * ((unsigned)OPP[i] * plane + rowoff), 0);
                 const unsigned mk = OPEN ? solids(y, near_sq, gA) : 0u;
+                if (OPEN) {
+                    bounce_select(mk, ny, y, ownv, p);
+                } else {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (solid(mk, k, y, 1, near_sq)) continue;  // a solid cell's results are never stored
+                    for (int k = 0; k < 4; ++k) {
+                        if (solid(mk, k, y, 1, near_sq)) continue;  // a solid cell's results are never stored
 #pragma unroll
-                    for (int i = 1; i < 9; ++i) {
-                        const int ys = y - CY[i];
-                        if (ys < 0 || ys >= ny) continue;
-                        if (solid(mk, k - CX[i], ys, 1 - CY[i], near_sq)) p[i][k] = ownv[i][k];
+                        for (int i = 1; i < 9; ++i) {
+                            const int ys = y - CY[i];
+                            if (ys < 0 || ys >= ny) continue;
+                            if (solid(mk, k - CX[i], ys, 1 - CY[i], near_sq)) p[i][k] = ownv[i][k];
+                        }
                     }
                 }
             }
@@ -368,15 +393,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
             if (near_b) {
+                if (OPEN) {
+                    f4 ownb[9];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (solid(mkb, k, r, 1, near_sq)) continue;
+                    for (int i = 1; i < 9; ++i) ownb[i] = *(const f4*)(own + OPP[i] * RING_ROW + RING_CELL0 + 4 * lane);
+                    bounce_select(mkb, ny, r, ownb, p);
+                } else {
 #pragma unroll
-                    for (int i = 1; i < 9; ++i) {
-                        const int rsrc = r - CY[i];
-                        if (rsrc < 0 || rsrc >= ny) continue;
-                        if (solid(mkb, k - CX[i], rsrc, 1 - CY[i], near_sq))
-                            p[i][k] = own[OPP[i] * RING_ROW + RING_CELL0 + 4 * lane + k];
+                    for (int k = 0; k < 4; ++k) {
+                        if (solid(mkb, k, r, 1, near_sq)) continue;
+#pragma unroll
+                        for (int i = 1; i < 9; ++i) {
+                            const int rsrc = r - CY[i];
+                            if (rsrc < 0 || rsrc >= ny) continue;
+                            if (solid(mkb, k - CX[i], rsrc, 1 - CY[i], near_sq))
+                                p[i][k] = own[OPP[i] * RING_ROW + RING_CELL0 + 4 * lane + k];
+                        }
                     }
                 }
             }
