@@ -57,11 +57,16 @@ __device__ __forceinline__ void lds_barrier() {
 // through L2 (not non-temporal): the neighbouring strip, on the same XCD and
 // near the same row, reads the words just outside this strip, and finds them
 // there (measured: 7 % instead of 12 % extra HBM fetch, 1.6 % faster).
-// OPEN: at the channel's ends the edge words come from the ghost block
-// (ghost != nullptr for the strips at x = 0 (left_end) and x = nx (right_end)).
+// OPEN: at the channel's ends the edge words come from the ghost block (rg,
+// [9][ny] floats: the strip at x = 0 (left_end) and the one ending at x = nx
+// (right_end)).  Every edge word is one vector load, from the state or from
+// the ghost block by a uniform choice of resource and offset: a scalar load
+// there, or a load whose register another kind of load also writes, makes
+// the compiler wait for every load in flight (the next row's prefetch
+// included).
 template <bool OPEN>
-__device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsrc_t rs, unsigned voff, int xl, int xr,
-                                         int y, RowLoads& L, const float* __restrict__ ghost, bool left_end,
+__device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rg,
+                                         unsigned voff, int xl, int xr, int y, RowLoads& L, bool left_end,
                                          bool right_end) {
     const unsigned plane = (unsigned)m.nx * (unsigned)m.ny;
     const unsigned rowoff = (unsigned)y * (unsigned)m.nx;
@@ -71,15 +76,24 @@ __device__ __forceinline__ void load_row(const MemberDev& m, __amdgpu_buffer_rsr
         const bool wall = ys < 0 || ys >= m.ny;
         const unsigned row = wall ? (unsigned)OPP[i] * plane + rowoff : (unsigned)i * plane + (unsigned)ys * (unsigned)m.nx;
         L.v[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4u * row, 0);
-        const unsigned gi = (unsigned)i * (unsigned)m.ny + (unsigned)(wall ? y : ys);
-        if (CX[i] == 1)
-            L.e[i] = (OPEN && left_end) ? ghost[gi]
-                                        : __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0));
-        else if (CX[i] == -1)
-            L.e[i] = (OPEN && right_end) ? ghost[gi]
-                                         : __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0));
-        else
-            L.e[i] = 0.0f;
+        if constexpr (OPEN) {
+            const unsigned gi = (unsigned)i * (unsigned)m.ny + (unsigned)(wall ? y : ys);
+            if (CX[i] != 0) {
+                const bool from_ghost = CX[i] == 1 ? left_end : right_end;
+                const unsigned xe = CX[i] == 1 ? (unsigned)xl : (unsigned)xr;
+                L.e[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    from_ghost ? rg : rs, from_ghost ? 0u : 4u * xe, from_ghost ? 4u * gi : 4u * row, 0));
+            } else {
+                L.e[i] = 0.0f;
+            }
+        } else {
+            if (CX[i] == 1)
+                L.e[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xl, 4u * row, 0));
+            else if (CX[i] == -1)
+                L.e[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4u * (unsigned)xr, 4u * row, 0));
+            else
+                L.e[i] = 0.0f;
+        }
     }
 }
 
@@ -163,6 +177,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const unsigned bytes = 36u * plane;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, (int)bytes, BUFFER_RSRC_WORD3);
     const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc((void*)dst, (short)0, (int)bytes, BUFFER_RSRC_WORD3);
+    // OPEN: the member's ghost block, [9][ny] floats (the inlet's +x movers, the outlet's -x movers)
+    const __amdgpu_buffer_rsrc_t rg =
+        OPEN ? __builtin_amdgcn_make_buffer_rsrc((void*)ghost, (short)0, (int)(36u * (unsigned)ny), BUFFER_RSRC_WORD3) : rs;
     const int base = tx * 256;
     const int x0 = base + 4 * lane;
     const unsigned voff = 4u * (unsigned)x0;
@@ -237,7 +254,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     // phase B of the last iteration reaches row yb - 1
     const int iters = SPLIT ? (yb + LAG - ya0 + NW - 1) / NW : (ny + LAG - 1) / NW + 1;
     RowLoads cur;
-    if ((SPLIT ? ya0 + wv : wv) < ya1) load_row<OPEN>(m, rs, voff, xl, xr, ya0 + wv, cur, ghost, left_end, right_end);
+    if ((SPLIT ? ya0 + wv : wv) < ya1) load_row<OPEN>(m, rs, rg, voff, xl, xr, ya0 + wv, cur, left_end, right_end);
 #pragma unroll 1
     for (int j = 0; j < iters; ++j) {
         const int y = ya0 + j * NW + wv;
@@ -310,8 +327,25 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
         }
+        // OPEN: the inlet's +x movers of row y, which lane 0 of the inlet strip
+        // puts in the ring's left slot for both steps.  Loaded by every strip and
+        // row (row clamped into the block), before the prefetch: loads issued on
+        // some paths only leave the compiler unable to count them, and it then
+        // waits for every load in flight, the prefetch included.
+        float gin[3] = {0.0f, 0.0f, 0.0f};
+        if (OPEN) {
+            const unsigned yg = (unsigned)min(y, ny - 1);
+#pragma unroll
+            for (int i = 0, n = 0; i < 9; ++i)
+                if (CX[i] == 1)
+                    gin[n++] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(rg, 0u, 4u * ((unsigned)i * (unsigned)ny + yg), 0));
+        }
         RowLoads nxt;
-        if (y + NW < ya1) load_row<OPEN>(m, rs, voff, xl, xr, y + NW, nxt, ghost, left_end, right_end);
+        if (OPEN)  // on every path (the row clamped; past the last row its words go unused): see gin
+            load_row<OPEN>(m, rs, rg, voff, xl, xr, min(y + NW, ya1 - 1), nxt, left_end, right_end);
+        else if (y + NW < ya1)
+            load_row<OPEN>(m, rs, rg, voff, xl, xr, y + NW, nxt, left_end, right_end);
         if (row_a) {
             float* row = ring + (y % RROWS) * 9 * RING_ROW;
             collide_row<MODEL, OPEN>(m, p, part0, near_sq, x0, y, sponge);
@@ -348,8 +382,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         for (int i = 0; i < 9; ++i) row[i * RING_ROW + at] = hv[i];
                 } else if (lane == 0) {  // the inlet's +x movers for both steps
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        if (CX[i] == 1) row[i * RING_ROW + at] = ghost[(unsigned)i * (unsigned)ny + (unsigned)y];
+                    for (int i = 0, n = 0; i < 9; ++i)
+                        if (CX[i] == 1) row[i * RING_ROW + at] = gin[n++];
                 }
             }
         }
