@@ -201,23 +201,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     if (grid_cols)
 #pragma unroll
         for (int j = 0; j < 6; ++j) gcols |= ((unsigned)(x0 - 1 + j - m.gx0) < (unsigned)m.bar ? 1u : 0u) << j;
-    // OPEN: which rows cross the grid's bars, one bit per row (ny <= 2048),
-    // filled once per workgroup so that no row test needs an integer division
-    __shared__ unsigned gbits[OPEN ? 64 : 1];
-    if (OPEN && grid_cols) {
-        for (int w = (int)threadIdx.x; w < (ny + 31) / 32; w += 64 * NW) {
-            unsigned bits = 0;
-            for (int k = 0; k < 32 && 32 * w + k < ny; ++k) bits |= (grid_row(m, 32 * w + k) ? 1u : 0u) << k;
-            gbits[w] = bits;
-        }
-        lds_barrier();
-    }
-    auto grow = [&](int yy) {  // row yy crosses the grid's bars (false outside the lattice)
-        return OPEN && grid_cols && yy >= 0 && yy < ny && ((gbits[yy >> 5] >> (yy & 31)) & 1u);
+    // OPEN: which rows cross the grid's bars.  Row yy does when yy >= bar/2 and
+    // its phase (yy - bar/2) mod 2 bar is below bar; the wave carries the phase of
+    // its row (a scalar, advanced by NW rows per iteration), so that no row test
+    // needs a division or a memory read
+    const int gper = 2 * m.bar, ghalf = m.bar >> 1;
+    auto grow_ph = [&](int yy, int ph) {  // false outside the lattice
+        return OPEN && grid_cols && yy >= ghalf && yy < ny && ph < m.bar;
     };
-    // bits 0, 1, 2: rows yy - 1, yy, yy + 1 cross the grid's bars (read once per row and phase)
-    auto rows3 = [&](int yy) -> unsigned {
-        return OPEN ? (grow(yy - 1) ? 1u : 0u) | (grow(yy) ? 2u : 0u) | (grow(yy + 1) ? 4u : 0u) : 0u;
+    // bits 0, 1, 2: rows yy - 1, yy, yy + 1 cross the grid's bars; ph: the phase of yy
+    auto rows3 = [&](int yy, int ph) -> unsigned {
+        if (!OPEN || !grid_cols) return 0u;
+        const int pm = ph == 0 ? gper - 1 : ph - 1, pp = ph + 1 == gper ? 0 : ph + 1;
+        return (grow_ph(yy - 1, pm) ? 1u : 0u) | (grow_ph(yy, ph) ? 2u : 0u) | (grow_ph(yy + 1, pp) ? 4u : 0u);
     };
     // OPEN: bit j: column x0 - 1 + j (j = 0..5) crosses the square
     unsigned sqcols = 0;
@@ -253,6 +249,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int ya0 = SPLIT ? max(ya - LAG, 0) : 0, ya1 = SPLIT ? min(yb + LAG, ny) : ny;  // phase A rows
     // phase B of the last iteration reaches row yb - 1
     const int iters = SPLIT ? (yb + LAG - ya0 + NW - 1) / NW : (ny + LAG - 1) / NW + 1;
+    // phase of the wave's phase-A row (once, by a division)
+    int gph = 0;
+    if (OPEN && grid_cols) {
+        const int r0 = (ya0 + wv - ghalf) % gper;
+        gph = r0 < 0 ? r0 + gper : r0;
+    }
     RowLoads cur;
     if ((SPLIT ? ya0 + wv : wv) < ya1) load_row<OPEN>(m, rs, rg, voff, xl, xr, ya0 + wv, cur, left_end, right_end);
 #pragma unroll 1
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         // flight.
         const bool row_a = y < ya1;
         const bool near_sq = row_a && sq_cols && y >= m.sy0 - 1 && y <= m.sy0 + m.ss;
-        const unsigned gA = row_a ? rows3(y) : 0u;
+        const unsigned gA = row_a ? rows3(y, gph) : 0u;
         const bool near_a = near_sq || gA != 0u;
         float hv[9];
         f4 p[9];
@@ -393,7 +395,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         if (r >= ya && r < yb) {
             const float* own = ring + (r % RROWS) * 9 * RING_ROW;
             const bool near_sq = sq_cols && r >= m.sy0 - 1 && r <= m.sy0 + m.ss;
-            const unsigned gB = rows3(r);
+            int phb = gph - LAG;  // the phase of row r = y - LAG
+            if (phb < 0) phb += gper;
+            if (phb < 0) phb += gper;
+            const unsigned gB = rows3(r, phb);
             const bool near_b = near_sq || gB != 0u;
             const unsigned mkb = OPEN && near_b ? solids(r, near_sq, gB) : 0u;
             f4 p[9];
@@ -467,6 +472,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
         lds_barrier();
         cur = nxt;
+        if (OPEN && grid_cols) {
+            gph += NW;
+            while (gph >= gper) gph -= gper;
+        }
     }
 }
 

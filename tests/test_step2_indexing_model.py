@@ -429,3 +429,60 @@ def test_ring_slots_hold_the_rows_phase_b_reads(nw, lag):
         assert ring_slots_ok(ny, nw, lag), ny
         for split in (1, 2, 5, 16):
             assert ring_slots_ok(ny, nw, lag, split), (ny, split)
+
+
+def _c_rem(a, b):
+    """C's a % b (the sign of a)."""
+    r = abs(a) % b
+    return -r if a < 0 else r
+
+
+def test_grid_row_phase_matches_the_row_test():
+    """The kernel does not test rows for the grid directly: each wave carries the phase
+    (y - bar/2) mod 2 bar of its phase-A row, set once by a division and advanced by NW rows per
+    iteration, and derives the bits for rows y - 1, y, y + 1 (phase A) and for r = y - LAG
+    (phase B) from it.  They equal the direct row test on every row, wave, lag and row range."""
+    def direct(ny, bar, yy):
+        r = yy - (bar >> 1)
+        return 0 <= yy < ny and bar > 0 and r >= 0 and r % (2 * bar) < bar
+
+    def bits_direct(ny, bar, yy):
+        return sum((1 << k) for k, d in enumerate((-1, 0, 1)) if direct(ny, bar, yy + d))
+
+    def bits_phase(ny, bar, yy, ph):
+        gper, ghalf = 2 * bar, bar >> 1
+        grow = lambda y, p: ghalf <= y < ny and p < bar
+        pm = gper - 1 if ph == 0 else ph - 1
+        pp = 0 if ph + 1 == gper else ph + 1
+        return (1 if grow(yy - 1, pm) else 0) | (2 if grow(yy, ph) else 0) | (4 if grow(yy + 1, pp) else 0)
+
+    checked = 0
+    for bar in range(1, 10):
+        gper, ghalf = 2 * bar, bar >> 1
+        for ny in (1, 2, 5, 37, 128):
+            for nw in (2, 4, 8):
+                for lag in (1, 2):
+                    for split in (None, 5, 16):
+                        segs = [(0, ny)] if split is None else [(a, min(a + split, ny)) for a in range(0, ny, split)]
+                        for ya, yb in segs:
+                            ya0, ya1 = (max(ya - lag, 0), min(yb + lag, ny)) if split else (0, ny)
+                            iters = (yb + lag - ya0 + nw - 1) // nw if split else (ny + lag - 1) // nw + 1
+                            for wv in range(nw):
+                                r0 = _c_rem(ya0 + wv - ghalf, gper)
+                                gph = r0 + gper if r0 < 0 else r0
+                                for j in range(iters):
+                                    y = ya0 + j * nw + wv
+                                    if y < ya1:
+                                        assert bits_phase(ny, bar, y, gph) == bits_direct(ny, bar, y)
+                                        checked += 1
+                                    r = y - lag
+                                    phb = gph - lag
+                                    phb += gper if phb < 0 else 0
+                                    phb += gper if phb < 0 else 0
+                                    if ya <= r < yb:
+                                        assert bits_phase(ny, bar, r, phb) == bits_direct(ny, bar, r), (bar, ny, nw, lag, r)
+                                        checked += 1
+                                    gph += nw
+                                    while gph >= gper:
+                                        gph -= gper
+    assert checked > 10000
