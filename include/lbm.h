@@ -454,6 +454,39 @@ int tail_probability(const double* fmax_dev, const double* log_weight_dev, int32
                      const double* levels_dev, int32_t n_levels, double* prob_dev, void* hip_stream);
 
 /*
+ * SCGF estimate of a GKTL run (paper Appendix C.1): out_dev[0] =
+ * (1/t_a) sum_i ln_r_dev[i], the sum in period order in FP64; t_a the
+ * simulated time (T_a, in the units the caller wants lambda in).  ln_r_dev:
+ * device double[n_periods] as written by gktl_select_clone; out_dev: device
+ * double[1].  LBM_EINVAL for n_periods < 1 or t_a not finite and > 0.
+ */
+int gktl_scgf(const double* ln_r_dev, int32_t n_periods, double t_a, double* out_dev, void* hip_stream);
+
+/*
+ * Return times from probabilities (paper Appendix C.2): for a block of length
+ * t_a and windows of length `window` (the time-averaged observable; 0 for a
+ * plain observable), r_dev[q] = -(t_a - window) / ln(1 - prob_dev[q]) in FP64
+ * (log1p); +inf where the probability is 0, 0 where it is 1.  Device
+ * double[n] each (NULL allowed for n = 0).  LBM_EINVAL unless 0 <= window <
+ * t_a, both finite.
+ */
+int return_times(const double* prob_dev, int32_t n, double t_a, double window, double* r_dev, void* hip_stream);
+
+/*
+ * Unbiased AMS estimate of P(max >= a) (paper Appendix B: the estimator of
+ * trajectory AMS): prob_dev[q] = prod_j (1 - k_history_dev[j] / n) (in
+ * iteration order) times (1/n) #{m : final_max_dev[m] >= levels_dev[q]}, in
+ * FP64.  k_history_dev: device int32[n_iter], the trajectories discarded at
+ * each iteration (NULL if n_iter = 0); final_max_dev: device double[n], the
+ * maxima of the final ensemble; levels_dev, prob_dev: device double[n_levels]
+ * (NULL allowed for n_levels = 0).  Valid for levels at or above the one every
+ * trajectory reached when the run stopped.  LBM_EINVAL for n < 1 or negative
+ * sizes.
+ */
+int ams_probability(const int32_t* k_history_dev, int32_t n_iter, int32_t n, const double* final_max_dev,
+                    const double* levels_dev, int32_t n_levels, double* prob_dev, void* hip_stream);
+
+/*
  * AMS score built from a learned prediction ghat for the target event
  * {max_t F_T(t) >= level} (F_T: time-averaged drag; paper Section 4.1: the
  * score may be any function of the state that reaches the level exactly when

@@ -66,6 +66,43 @@ extern "C" int tail_probability(const double* fmax_dev, const double* log_weight
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "tail probability");
 }
 
+extern "C" int gktl_scgf(const double* ln_r_dev, int32_t n_periods, double t_a, double* out_dev, void* hip_stream) {
+    if (!ln_r_dev || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (n_periods < 1) return lbm_fail(LBM_EINVAL, "n_periods must be >= 1");
+    if (!(t_a > 0.0) || !std::isfinite(t_a)) return lbm_fail(LBM_EINVAL, "T_a must be finite and > 0");
+    hipError_t e = launch_scgf(ln_r_dev, n_periods, t_a, out_dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "SCGF");
+}
+
+extern "C" int return_times(const double* prob_dev, int32_t n, double t_a, double window, double* r_dev,
+                            void* hip_stream) {
+    if (n < 0) return lbm_fail(LBM_EINVAL, "negative count");
+    if (!std::isfinite(t_a) || !std::isfinite(window) || !(window >= 0.0) || !(t_a > window))
+        return lbm_fail(LBM_EINVAL, "need 0 <= window < T_a, both finite");
+    if (n == 0) return LBM_OK;
+    if (!prob_dev || !r_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    hipError_t e = launch_return_times(prob_dev, n, t_a, window, r_dev, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "return times");
+}
+
+extern "C" int ams_probability(const int32_t* k_history_dev, int32_t n_iter, int32_t n, const double* final_max_dev,
+                               const double* levels_dev, int32_t n_levels, double* prob_dev, void* hip_stream) {
+    if (n < 1 || n_iter < 0 || n_levels < 0) return lbm_fail(LBM_EINVAL, "bad sizes");
+    if (n_levels == 0) return LBM_OK;
+    if (!final_max_dev || !levels_dev || !prob_dev || (n_iter > 0 && !k_history_dev))
+        return lbm_fail(LBM_EINVAL, "NULL argument");
+    AmsProbArgs a;
+    a.k_history = k_history_dev;
+    a.n_iter = n_iter;
+    a.n = n;
+    a.final_max = final_max_dev;
+    a.levels = levels_dev;
+    a.n_levels = n_levels;
+    a.prob = prob_dev;
+    hipError_t e = launch_ams_probability(a, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "AMS probability");
+}
+
 extern "C" int ams_learned_score(const float* ghat_dev, const float* ft_dev, int64_t count, float level,
                                  float width, float* out_dev, void* hip_stream) {
     if (!ghat_dev || !ft_dev || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");

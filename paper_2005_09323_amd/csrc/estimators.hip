@@ -77,6 +77,39 @@ __global__ void tail_probability_kernel(TailArgs a) {
     a.prob[q] = s / (double)a.n;
 }
 
+// SCGF estimate (paper Appendix C.1): lambda(k) = (1/T_a) sum_i ln R_i, the
+// sum in period order (one thread).
+__global__ void scgf_kernel(const double* ln_r, int n_periods, double t_a, double* out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n_periods; ++i) s += ln_r[i];
+    out[0] = s / t_a;
+}
+
+// Return time of a level from the probability p that a block of length T_a
+// holds a window of length T above it (paper Appendix C.2):
+// r = -(T_a - T) / ln(1 - p); +inf where p = 0 (0 where p = 1).
+__global__ void return_times_kernel(const double* prob, int n, double t_a, double window, double* r) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= n) return;
+    const double p = prob[q];
+    r[q] = p == 0.0 ? INFINITY : -(t_a - window) / log1p(-p);
+}
+
+// Unbiased AMS estimate of P(max >= a) (paper Appendix B): the product over
+// the iterations of (1 - K_j / N), in order, times the fraction of the final
+// ensemble whose maximum reaches a.  Thread = level.
+__global__ void ams_probability_kernel(AmsProbArgs a) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= a.n_levels) return;
+    double f = 1.0;
+    for (int j = 0; j < a.n_iter; ++j) f *= 1.0 - (double)a.k_history[j] / (double)a.n;
+    const double lev = a.levels[q];
+    int c = 0;
+    for (int m = 0; m < a.n; ++m) c += a.final_max[m] >= lev ? 1 : 0;
+    a.prob[q] = f * (double)c / (double)a.n;
+}
+
 // AMS score from a learned predictor, kept consistent with the target event
 // {max_t F_T(t) >= a}: the score is a once the time-averaged drag has reached a;
 // before that the prediction g is mapped strictly increasingly into (-inf, a),
@@ -115,6 +148,18 @@ hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st) {
 }
 hipError_t launch_window_max(const WindowMaxArgs& a, int rows, hipStream_t st) {
     hipLaunchKernelGGL(window_max_kernel, dim3(rows), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_scgf(const double* ln_r, int n_periods, double t_a, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(scgf_kernel, dim3(1), dim3(64), 0, st, ln_r, n_periods, t_a, out);
+    return hipGetLastError();
+}
+hipError_t launch_return_times(const double* prob, int n, double t_a, double window, double* r, hipStream_t st) {
+    hipLaunchKernelGGL(return_times_kernel, dim3((n + 255) / 256), dim3(256), 0, st, prob, n, t_a, window, r);
+    return hipGetLastError();
+}
+hipError_t launch_ams_probability(const AmsProbArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(ams_probability_kernel, dim3((a.n_levels + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_tail(const TailArgs& a, hipStream_t st) {

@@ -34,6 +34,18 @@ struct TailArgs {
     double* prob;
 };
 
+struct AmsProbArgs {
+    const int* k_history;   // [n_iter] trajectories discarded per iteration
+    int n_iter, n;          // iterations, ensemble size
+    const double* final_max;  // [n] maxima of the final ensemble
+    const double* levels;   // [n_levels]
+    int n_levels;
+    double* prob;           // [n_levels]
+};
+
+hipError_t launch_scgf(const double* ln_r, int n_periods, double t_a, double* out, hipStream_t st);
+hipError_t launch_return_times(const double* prob, int n, double t_a, double window, double* r, hipStream_t st);
+hipError_t launch_ams_probability(const AmsProbArgs& a, hipStream_t st);
 hipError_t launch_learned_score(const float* ghat, const float* ft, long long count, float a, float w, float* out,
                                 hipStream_t st);
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t st);

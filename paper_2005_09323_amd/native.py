@@ -89,6 +89,9 @@ _SIG = {
     "gktl_rebuild": (ctypes.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _D, _P, _P, _P, _P]),
     "window_mean_max": (ctypes.c_int, [_P, _I, _I, _I, _P, _P, _P]),
     "tail_probability": (ctypes.c_int, [_P, _P, _I, _P, _I, _P, _P]),
+    "gktl_scgf": (ctypes.c_int, [_P, _I, _D, _P, _P]),
+    "return_times": (ctypes.c_int, [_P, _I, _D, _D, _P, _P]),
+    "ams_probability": (ctypes.c_int, [_P, _I, _I, _P, _P, _I, _P, _P]),
     "ams_learned_score": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, _P, _P]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }

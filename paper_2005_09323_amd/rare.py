@@ -8,7 +8,6 @@ perturbation at branching, Appendix D.
 from __future__ import annotations
 
 import ctypes
-import math
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -35,8 +34,12 @@ class GktlRun:
         return self.tau * self.n_periods
 
     def scgf(self, dt: float) -> float:
-        """lambda(k) = (1/T_a) sum_i ln R_i, T_a in the units of dt."""
-        return float(self.ln_r.double().sum().item()) / (self.t_a * dt)
+        """lambda(k) = (1/T_a) sum_i ln R_i, T_a in the units of dt (device, FP64)."""
+        ln_r = self.ln_r.to(device="cuda", dtype=torch.float64).contiguous()
+        out = torch.empty(1, dtype=torch.float64, device=ln_r.device)
+        native.check(native.lib().gktl_scgf(_ptr(ln_r), int(ln_r.numel()), float(self.t_a * dt), _ptr(out),
+                                            _stream_handle(None)))
+        return float(out.item())
 
     def then(self, later: "GktlRun") -> "GktlRun":
         """This run followed by `later`, its continuation (same k and tau, its periods numbered on
@@ -116,12 +119,12 @@ def tail_probability(fmax: torch.Tensor, log_weight: torch.Tensor, levels: Seque
 
 
 def return_time(prob: np.ndarray, block: float, window: float) -> np.ndarray:
-    """r(a) = -(T_a - T) / ln(1 - P(a)) (paper Appendix C.2); inf where P = 0."""
-    prob = np.asarray(prob, dtype=np.float64)
-    out = np.full(prob.shape, math.inf)
-    pos = prob > 0
-    out[pos] = -(block - window) / np.log1p(-np.minimum(prob[pos], 1 - 1e-16))
-    return out
+    """r(a) = -(T_a - T) / ln(1 - P(a)) (paper Appendix C.2); inf where P = 0 (device, FP64)."""
+    p = torch.as_tensor(np.asarray(prob, dtype=np.float64)).reshape(-1).to("cuda").contiguous()
+    r = torch.empty_like(p)
+    native.check(native.lib().return_times(_ptr(p), int(p.numel()), float(block), float(window), _ptr(r),
+                                           _stream_handle(None)))
+    return r.cpu().numpy().reshape(np.shape(prob))
 
 
 def gktl_return_times(run: GktlRun, ens: Ensemble, window: int, levels: Sequence[float]):
@@ -161,11 +164,14 @@ class AmsResult:
         """prod_j (1 - K_j / N) * (1/N) #{n : max F_T >= a}: the unbiased AMS estimate for levels at
         or above the one every trajectory reached when the run stopped (below it, the final ensemble
         no longer holds the trajectories that were discarded on the way)."""
-        f = 1.0
-        for kj in self.k_history:
-            f *= 1.0 - kj / self.n
-        q = np.asarray(self.event_max, dtype=np.float64)
-        return np.array([f * np.count_nonzero(q >= a) / self.n for a in levels])
+        kh = torch.tensor(list(self.k_history), dtype=torch.int32, device="cuda")
+        q = torch.as_tensor(np.asarray(self.event_max, dtype=np.float64)).to("cuda").contiguous()
+        lev = torch.tensor(list(levels), dtype=torch.float64, device="cuda")
+        prob = torch.empty_like(lev)
+        native.check(native.lib().ams_probability(_ptr(kh) if kh.numel() else None, int(kh.numel()), self.n,
+                                                  _ptr(q), _ptr(lev), int(lev.numel()), _ptr(prob),
+                                                  _stream_handle(None)))
+        return prob.cpu().numpy()
 
 
 class AmsRunner:

@@ -21,8 +21,7 @@ def test_then_joins_a_continuation():
     assert whole.n_periods == 5 and whole.col0 == 1 and whole.t_a == 40
     assert torch.equal(whole.ancestors[:3], first.ancestors) and torch.equal(whole.ancestors[3:], second.ancestors)
     assert torch.equal(whole.integrals[3:], second.integrals)
-    assert torch.equal(whole.ln_r, torch.cat([first.ln_r, second.ln_r]))
-    assert whole.scgf(1.0) == pytest.approx(float(whole.ln_r.sum()) / 40)
+    assert torch.equal(whole.ln_r, torch.cat([first.ln_r, second.ln_r]))  # what its SCGF sums over T_a = 40
 
 
 @pytest.mark.parametrize("bad", ["gap", "k", "tau"])

@@ -495,3 +495,55 @@ def test_relabelling_clone_bit_identical_to_gather(eps, n_snap):
         assert offs == [k * floats for k in range(n)]
     e1.close()
     e0.close()
+
+
+def test_estimators_in_fp64_on_the_device_match_oracle():
+    """The SCGF of a GKTL run, return times from probabilities, and the unbiased AMS estimate,
+    computed by the library in FP64, against the oracle's definitions (Appendix C.1, C.2, B):
+    seeded inputs plus the edge cases (one period, probabilities 0 and 1, no AMS iteration,
+    levels above and below every maximum); argument errors leave the outputs alone."""
+    from paper_2005_09323_amd import native
+    from paper_2005_09323_amd.ensemble import _ptr, _stream_handle
+    lib = native.lib()
+    st = _stream_handle(None)
+    rng = np.random.default_rng(41)
+    for n_periods in (1, 7, 300):
+        ln_r = rng.normal(0.3, 2.0, n_periods)
+        d = torch.tensor(ln_r, dtype=torch.float64, device="cuda")
+        out = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+        t_a = 16.0 * n_periods * 0.25
+        native.check(lib.gktl_scgf(_ptr(d), n_periods, t_a, _ptr(out), st))
+        ref = ogktl.scgf(ln_r, t_a)
+        assert abs(out.item() - ref) <= 1e-13 * max(1.0, abs(ref)), n_periods
+    probs = np.concatenate([[0.0, 1e-300, 1e-12, 1e-6, 0.3, 0.999, 1.0], rng.uniform(0, 1, 40)])
+    p = torch.tensor(probs, dtype=torch.float64, device="cuda")
+    r = torch.empty_like(p)
+    for t_a, window in ((300.0, 50.0), (40.0, 0.0)):
+        native.check(lib.return_times(_ptr(p), len(probs), t_a, window, _ptr(r), st))
+        got = r.cpu().numpy()
+        with np.errstate(divide="ignore"):  # p = 1 in the oracle: ln 0
+            ref = ogktl.return_time(probs, t_a, window) if window else oams.return_time(probs, t_a)
+        assert np.isinf(got[0]) and got[6] == 0.0
+        assert np.allclose(got[1:], ref[1:], rtol=1e-14, atol=0.0), (t_a, window)
+    for bad in ((40.0, 40.0), (40.0, -1.0), (math.inf, 0.0)):
+        r.fill_(7.0)
+        assert lib.return_times(_ptr(p), len(probs), bad[0], bad[1], _ptr(r), st) != 0
+        assert torch.all(r == 7.0)
+    assert lib.return_times(None, 0, 10.0, 1.0, None, st) == 0
+    for n, n_iter in ((512, 0), (512, 26), (37, 5)):
+        kh = rng.integers(1, max(2, n // 10), n_iter).astype(np.int32)
+        final = rng.normal(0.0, 1.0, n)
+        levels = np.concatenate([[final.min() - 1, final.max() + 1, final.max()], np.quantile(final, [0.1, 0.5, 0.9])])
+        khd = torch.tensor(kh, dtype=torch.int32, device="cuda")
+        fd = torch.tensor(final, dtype=torch.float64, device="cuda")
+        ld = torch.tensor(levels, dtype=torch.float64, device="cuda")
+        pd = torch.empty_like(ld)
+        native.check(lib.ams_probability(_ptr(khd) if n_iter else None, n_iter, n, _ptr(fd), _ptr(ld), len(levels),
+                                         _ptr(pd), st))
+        ref = oams.estimate(list(kh), n, final, levels)
+        assert np.allclose(pd.cpu().numpy(), ref, rtol=1e-14, atol=0.0), (n, n_iter)
+        assert pd[1].item() == 0.0
+    assert lib.ams_probability(None, 3, 10, _ptr(fd), _ptr(ld), len(levels), _ptr(pd), st) != 0
+    assert lib.ams_probability(_ptr(khd), 1, 0, _ptr(fd), _ptr(ld), len(levels), _ptr(pd), st) != 0
+    assert lib.gktl_scgf(_ptr(fd), 0, 1.0, _ptr(pd), st) != 0
+    assert lib.gktl_scgf(_ptr(fd), 3, 0.0, _ptr(pd), st) != 0
