@@ -213,8 +213,12 @@ int lbm_face_diagnostics(const lbm_ctx* ctx, double* out_dev);
  * receive the central moments of Guo's source weighted by (1 - s/2); the
  * shear moments k20 - k02 and k11 relax at 1/tau (the viscosity), the trace
  * k20 + k02 at s_bulk, k21 and k12 at s_third, k22 at s_fourth.  Rates in
- * (0, 2); with all three equal to 1/tau the result is BGK's.  Call before
- * lbm_init (its step 0 collides too); synchronises the context's stream.
+ * (0, 2); with all three equal to 1/tau the result is BGK's.  With all three
+ * equal to 1 (the paper's setting) the library evaluates the same collision
+ * in a shorter form (the trace and the third- and fourth-order moments leave
+ * it at closed-form values, so their pre-collision values are not formed):
+ * equal up to FP64 rounding.  Call before lbm_init (its step 0 collides
+ * too); synchronises the context's stream.
  */
 int lbm_set_collision(lbm_ctx* ctx, int32_t model, double s_bulk, double s_third, double s_fourth);
 

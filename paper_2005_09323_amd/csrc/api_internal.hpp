@@ -85,7 +85,7 @@ struct lbm_ctx {
     int chunk = 64;
     double mu = 0.0, sigma = 1.0, dt = 1.0;
     int tile_id = lbm::DEFAULT_TILE;
-    int model = 0;  // collision: 0 BGK, 1 central moments (every member)
+    int model = 0;  // collision: 0 BGK, 1 central moments, 2 the same with unit bulk/third/fourth rates
     // open channel (every member): inlet, grid, sponge, outlet ghost columns
     bool open = false;
     float* d_ghost = nullptr;  // [member][9][ny] floats

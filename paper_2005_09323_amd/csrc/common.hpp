@@ -69,7 +69,7 @@ struct MemberDev {
     double gf3, gf9;      // (1 - omega/2) * 3F and (1 - omega/2) * 9F (Guo source)
     double force;         // F (central-moment collision)
     double sb, s3, s4;    // central-moment rates: trace, third order, fourth order
-    int model;            // 0: BGK; 1: central moments
+    int model;            // 0: BGK; 1: central moments; 2: central moments, unit bulk/third/fourth rates
     int open;             // 1: inlet, entrance grid, sponge and outlet instead of periodic x
     long long off;        // first float of the member in a population buffer
     long long part_off;   // first float of the member in the drag-partial buffer

@@ -614,9 +614,11 @@ extern "C" int lbm_set_collision(lbm_ctx* c, int32_t model, double s_bulk, doubl
     if (model == 1)
         for (double s : {s_bulk, s_third, s_fourth})
             if (!(s > 0.0 && s < 2.0)) return lbm_fail(LBM_EINVAL, "relaxation rate %g outside (0, 2)", s);
-    c->model = model;
+    // unit bulk, third- and fourth-order rates: the shorter evaluation of the same collision
+    const int internal = model == 1 && s_bulk == 1.0 && s_third == 1.0 && s_fourth == 1.0 ? 2 : model;
+    c->model = internal;
     for (auto& m : c->h_members) {
-        m.model = model;
+        m.model = internal;
         if (model == 1) {
             m.sb = s_bulk;
             m.s3 = s_third;

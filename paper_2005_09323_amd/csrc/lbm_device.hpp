@@ -169,18 +169,92 @@ __device__ __forceinline__ double cm_guo(const MemberDev& m, float d[9], unsigne
     return drag;
 }
 
+// The central-moment collision above when the bulk, third- and fourth-order
+// rates are all 1 (the setting of the paper's turbulent runs): the trace
+// k20 + k02 and the third- and fourth-order central moments then leave the
+// collision at their equilibrium-plus-forcing values, closed forms of rho, u
+// and F, so the pre-collision k21, k12 and k22 are never needed.  The
+// post-collision raw moments follow by the binomial shift and the
+// populations by the inverse moment matrix, all as deviations from the rest
+// state (the weights' moments 1, 1/3, 1/3, 1/9 subtracted analytically, so a
+// state at rest stays exactly at rest).  Equal to cm_guo with those rates up
+// to FP64 rounding; contraction pinned as there.
+__device__ __forceinline__ double cm1_guo(const MemberDev& m, float d[9], unsigned links) {
+#pragma clang fp contract(on)
+    const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+    const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
+    const double dr = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;  // rho - 1
+    const double diag = (d5 + d6) + (d7 + d8);
+    const double rho = 1.0 + dr;
+    const double jx = ((d1 - d3) + (d5 - d6)) + (d8 - d7);
+    const double jy = ((d2 - d4) + (d5 - d7)) + (d6 - d8);
+    const double dm20 = (d1 + d3) + diag;  // m20 - 1/3
+    const double dm02 = (d2 + d4) + diag;  // m02 - 1/3
+    const double m11 = (d5 - d6) + (d7 - d8);
+    double inv = (double)__builtin_amdgcn_rcpf((float)rho);
+    inv = inv * (2.0 - rho * inv);
+    inv = inv * (2.0 - rho * inv);
+    const double F = m.force;
+    const double ux = (jx + m.half_fx) * inv, uy = jy * inv;
+    const double uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    // second order: k20 - k02 and k11 relax at omega, k20 + k02 goes to 2 rho / 3
+    const double kd = ((dm20 - dm02) - 2.0 * ux * jx + 2.0 * uy * jy) + (uxx - uyy) * rho;
+    const double k11 = m11 - ux * jy - uy * jx + uxy * rho;
+    const double om1 = 1.0 - m.omega;
+    const double a = 0.5 * om1 * kd;
+    const double k11s = om1 * k11;
+    const double k20s = rho * (1.0 / 3.0) + a, k02s = rho * (1.0 / 3.0) - a;
+    // third and fourth order: equilibrium plus (1/2) of the source's central moments
+    const double k21s = -(rho * uxx * uy + uxy * F);
+    const double k12s = 0.5 * F * ((1.0 / 3.0) - uyy) - rho * ux * uyy;
+    const double dk22s = dr * (1.0 / 9.0) + 3.0 * rho * uxx * uyy + 2.0 * ux * uyy * F;  // k22* - 1/9
+    // post-collision raw moments (k10* = F/2, k01* = 0), as deviations from rest
+    const double m10s = jx + F;
+    const double dm20s = dr * (1.0 / 3.0) + a + ux * F + uxx * rho;
+    const double dm02s = dr * (1.0 / 3.0) - a + uyy * rho;
+    const double m11s = k11s + 0.5 * uy * F + uxy * rho;
+    const double m21s = k21s + 2.0 * ux * k11s + uy * k20s + uxy * F + uxx * uy * rho;
+    const double m12s = k12s + 2.0 * uy * k11s + ux * k02s + 0.5 * uyy * F + ux * uyy * rho;
+    const double dm22s = (dk22s + 2.0 * ux * k12s + 2.0 * uy * k21s) + (uxx * k02s + uyy * k20s + 4.0 * uxy * k11s) +
+                         (ux * uyy * F + uxx * uyy * rho);
+    // populations (inverse of the raw-moment matrix)
+    const double o0 = (dr - dm20s) - (dm02s - dm22s);
+    const double o1 = 0.5 * ((m10s + dm20s) - (m12s + dm22s));
+    const double o3 = 0.5 * ((dm20s - m10s) + (m12s - dm22s));
+    const double o2 = 0.5 * ((jy + dm02s) - (m21s + dm22s));
+    const double o4 = 0.5 * ((dm02s - jy) + (m21s - dm22s));
+    const double o5 = 0.25 * ((m11s + m21s) + (m12s + dm22s));
+    const double o6 = 0.25 * ((m21s - m11s) + (dm22s - m12s));
+    const double o7 = 0.25 * ((m11s - m21s) + (dm22s - m12s));
+    const double o8 = 0.25 * ((m12s - m11s) + (dm22s - m21s));
+    double drag = 0.0;
+    if (links) {
+        if ((links >> 1) & 1u) drag += 2.0 * o1;
+        if ((links >> 3) & 1u) drag -= 2.0 * o3;
+        if ((links >> 5) & 1u) drag += 2.0 * o5;
+        if ((links >> 6) & 1u) drag -= 2.0 * o6;
+        if ((links >> 7) & 1u) drag -= 2.0 * o7;
+        if ((links >> 8) & 1u) drag += 2.0 * o8;
+    }
+    d[0] = (float)o0; d[1] = (float)o1; d[2] = (float)o2; d[3] = (float)o3; d[4] = (float)o4;
+    d[5] = (float)o5; d[6] = (float)o6; d[7] = (float)o7; d[8] = (float)o8;
+    return drag;
+}
+
 // The collision of a kernel instantiated for one model (0: BGK, 1: central
-// moments); the step kernels are compiled once per model so that each keeps
-// its own register allocation.
+// moments, 2: central moments with unit bulk, third- and fourth-order rates);
+// the step kernels are compiled once per model so that each keeps its own
+// register allocation.
 template <int MODEL>
 __device__ __forceinline__ double collide_cell(const MemberDev& m, float d[9], unsigned links) {
-    if constexpr (MODEL == 1) return cm_guo(m, d, links);
+    if constexpr (MODEL == 2) return cm1_guo(m, d, links);
+    else if constexpr (MODEL == 1) return cm_guo(m, d, links);
     else return bgk_guo(m, d, links);
 }
 
 // The member's own model, decided at run time (the one-off initial step).
 __device__ __forceinline__ double collide_member(const MemberDev& m, float d[9], unsigned links) {
-    return m.model ? cm_guo(m, d, links) : bgk_guo(m, d, links);
+    return m.model == 2 ? cm1_guo(m, d, links) : (m.model ? cm_guo(m, d, links) : bgk_guo(m, d, links));
 }
 
 // The nine pulled populations of one cell (x, y) from the state at t, with

@@ -380,10 +380,12 @@ template <int TYT, int R>
 static hipError_t launch_step_t(const StepArgs& a, int model, hipStream_t st) {
     const dim3 grid(a.total_blocks), block(64 * TYT);
     if (a.ghost) {
-        if (model == 1) hipLaunchKernelGGL((step_kernel<TYT, R, 1, true>), grid, block, 0, st, a);
+        if (model == 2) hipLaunchKernelGGL((step_kernel<TYT, R, 2, true>), grid, block, 0, st, a);
+        else if (model == 1) hipLaunchKernelGGL((step_kernel<TYT, R, 1, true>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((step_kernel<TYT, R, 0, true>), grid, block, 0, st, a);
     } else {
-        if (model == 1) hipLaunchKernelGGL((step_kernel<TYT, R, 1, false>), grid, block, 0, st, a);
+        if (model == 2) hipLaunchKernelGGL((step_kernel<TYT, R, 2, false>), grid, block, 0, st, a);
+        else if (model == 1) hipLaunchKernelGGL((step_kernel<TYT, R, 1, false>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((step_kernel<TYT, R, 0, false>), grid, block, 0, st, a);
     }
     return hipGetLastError();

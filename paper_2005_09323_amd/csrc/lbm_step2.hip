@@ -483,10 +483,12 @@ template <int NW, bool SPLIT>
 static void launch_step2_s(const StepArgs& a, int model, hipStream_t st) {
     const dim3 grid(a.total_blocks), block(64 * NW);
     if (a.ghost) {
-        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, true, SPLIT>), grid, block, 0, st, a);
+        if (model == 2) hipLaunchKernelGGL((step2_kernel<NW, 2, true, SPLIT>), grid, block, 0, st, a);
+        else if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, true, SPLIT>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((step2_kernel<NW, 0, true, SPLIT>), grid, block, 0, st, a);
     } else {
-        if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, false, SPLIT>), grid, block, 0, st, a);
+        if (model == 2) hipLaunchKernelGGL((step2_kernel<NW, 2, false, SPLIT>), grid, block, 0, st, a);
+        else if (model == 1) hipLaunchKernelGGL((step2_kernel<NW, 1, false, SPLIT>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((step2_kernel<NW, 0, false, SPLIT>), grid, block, 0, st, a);
     }
 }
