@@ -490,12 +490,30 @@ def open_channel_stats(flow: OpenFlow, n: int, burn: int, steps: int, out=None, 
     return rec
 
 
+def lattice_rates(flow, counts=(32, 512), steps: int = 1024, out=None, seed: int = 3):
+    """Lattice rate of the flow's ensemble at the member counts AMS steps (all members, then the
+    re-simulated ones): milliseconds per step and GLUPS over all cells, after 500 untimed steps."""
+    for n in counts:
+        ens = flow.ensemble(n, steps + 2)
+        flow.start(ens, seed)
+        ens.step(500)
+        ens.set_time(1)
+        t0 = _sync_time()
+        ens.step(steps)
+        ms = (_sync_time() - t0) * 1e3 / steps
+        _emit(out, {"experiment": "lattice_rate", "members": n, "nx": flow.nx, "ny": flow.ny, "steps": steps,
+                    "ms_per_step": ms, "GLUPS": n * flow.nx * flow.ny / ms / 1e6,
+                    "steps_per_launch": ens.launch_steps()})
+        ens.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["gktl", "ams", "all", "open", "score", "cfg3", "cfg4"],
+    ap.add_argument("which", choices=["gktl", "ams", "all", "open", "score", "cfg3", "cfg4", "rates"],
                     help="cfg3: GKTL on the 256 x 1024 x 256 workload (period 256, T 2048, T_a 6144, "
                          "k 0.5/1/2, dt 1/512); cfg4: AMS with the plain and the learned score on the "
-                         "512 x 512 x 128 workload")
+                         "512 x 512 x 128 workload; rates: the lattice rate of the AMS workload's flow "
+                         "at 32 and 512 members")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--repeats", type=int, default=10)
     ap.add_argument("--flow", choices=["channel", "open"], default="channel",
@@ -537,6 +555,8 @@ def main(argv=None):
                         direct_steps=args.direct_steps, eps=args.eps, n_src=256,
                         fixed=dict(tau=256, window=2048, t_a=6144, dt=1.0 / 512.0),
                         zs=(1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0))
+    if args.which == "rates":
+        lattice_rates(ams_flow(), out=args.out)
     if args.which == "cfg4":
         fl = ams_flow()
         if args.burn is not None:
