@@ -22,6 +22,7 @@ hipError_t fill_double(double* p, int n, double v, hipStream_t st);
 hipError_t set_int(int* p, int v, hipStream_t st);
 // p[m] = bit m; list (if non-null) = the set members in increasing order
 hipError_t set_bits(int* p, int* list, int n, const MaskBits& bits, hipStream_t st);
+hipError_t fill_iota(int* p, int n, hipStream_t st);  // p[i] = i
 
 }  // namespace lbm
 
@@ -72,7 +73,7 @@ struct lbm_ctx {
     int* d_parity = nullptr;
     int* d_cursor = nullptr;
     int* d_active = nullptr;
-    int* d_active_list = nullptr;  // active members in order (valid while n_active < n)
+    int* d_active_list = nullptr;  // the n_active active members in ascending order
     int n_active = 0;
     int* d_flags = nullptr;
     std::vector<int> h_parity, h_cursor, h_active;

@@ -97,6 +97,7 @@ extern "C" int score_features(const lbm_ctx* c, int32_t m0, int32_t n, int32_t p
     a.pop0 = c->pop[0];
     a.pop1 = c->pop[1];
     a.m0 = m0;
+    a.list = nullptr;
     a.px0 = px0;
     a.py0 = py0;
     a.patch = patch;
@@ -105,6 +106,38 @@ extern "C" int score_features(const lbm_ctx* c, int32_t m0, int32_t n, int32_t p
     a.rho_scale = rho_scale;
     a.out = out_dev;
     hipError_t e = launch_features(a, n, c->stream);
+    return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "feature kernel");
+}
+
+extern "C" int score_features_active(const lbm_ctx* c, int32_t px0, int32_t py0, int32_t patch, int32_t pool,
+                                     double u_scale, double rho_scale, float* out_dev, int32_t* n_rows) {
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
+    if (pool < 1 || patch < pool || patch % pool || patch / pool > 16)
+        return lbm_fail(LBM_EINVAL, "patch must be a multiple of pool with patch/pool <= 16");
+    if (c->n_active > 0 && !out_dev) return lbm_fail(LBM_EINVAL, "NULL output");
+    for (int m = 0; m < c->n; ++m) {
+        if (!c->h_active[m]) continue;
+        const lbm_member_desc& d = c->desc[m];
+        if (px0 < 0 || py0 < 0 || px0 + patch > d.nx || py0 + patch > d.ny)
+            return lbm_fail(LBM_EINVAL, "patch outside member %d", m);
+    }
+    if (n_rows) *n_rows = c->n_active;
+    if (c->n_active == 0) return LBM_OK;
+    FeatureArgs a;
+    a.members = c->d_members;
+    a.parity = c->d_parity;
+    a.pop0 = c->pop[0];
+    a.pop1 = c->pop[1];
+    a.m0 = 0;
+    a.list = c->d_active_list;
+    a.px0 = px0;
+    a.py0 = py0;
+    a.patch = patch;
+    a.pool = pool;
+    a.u_scale = u_scale;
+    a.rho_scale = rho_scale;
+    a.out = out_dev;
+    hipError_t e = launch_features(a, c->n_active, c->stream);
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "feature kernel");
 }
 

@@ -699,7 +699,7 @@ __global__ __launch_bounds__(256) void cnn_adam_kernel(AdamArgs a) {
 
 // Near-wake features of members m0 .. m0+n-1: block = member, thread = pooled pixel.
 __global__ __launch_bounds__(256) void features_kernel(FeatureArgs a) {
-    const int mi = a.m0 + (int)blockIdx.x;
+    const int mi = a.list ? a.list[blockIdx.x] : a.m0 + (int)blockIdx.x;
     const MemberDev m = a.members[mi];
     const int side = a.patch / a.pool;
     const int t = (int)threadIdx.x;

@@ -84,6 +84,7 @@ struct FeatureArgs {
     const float* pop0;
     const float* pop1;
     int m0;
+    const int* list;  // member of output row b: list[b], or m0 + b where null
     int px0, py0, patch, pool;
     double u_scale, rho_scale;
     float* out;  // [n][3][patch/pool][patch/pool]

@@ -49,6 +49,10 @@ __global__ void fill_double_kernel(double* p, int n, double v) {
     if (i < n) p[i] = v;
 }
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
+__global__ void iota_kernel(int* p, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = i;
+}
 __global__ void set_bits_kernel(int* p, int* list, int n, MaskBits bits) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
@@ -69,6 +73,11 @@ hipError_t fill_int(int* p, int n, int v, hipStream_t st) {
 hipError_t fill_double(double* p, int n, double v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_double_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t fill_iota(int* p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 hipError_t set_int(int* p, int v, hipStream_t st) {
@@ -321,6 +330,7 @@ extern "C" int lbm_create(lbm_ctx** out, const lbm_member_desc* members, int32_t
     if ((e = fill_int(c->d_parity, n_members, 0, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_cursor, n_members, 0, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_active, n_members, 1, c->stream)) != hipSuccess ||
+        (e = fill_iota(c->d_active_list, n_members, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_flags, n_members, 0, c->stream)) != hipSuccess) {
         lbm_destroy(c);
         return lbm_hip_fail(e, "initialising bookkeeping");
@@ -381,6 +391,7 @@ extern "C" int lbm_init_flow(lbm_ctx* c, uint64_t seed, double noise_amp, double
     if ((e = fill_int(c->d_parity, c->n, 0, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_cursor, c->n, 0, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_active, c->n, 1, c->stream)) != hipSuccess ||
+        (e = fill_iota(c->d_active_list, c->n, c->stream)) != hipSuccess ||
         (e = fill_int(c->d_flags, c->n, 0, c->stream)) != hipSuccess ||
         (e = fill_double(c->accum, c->n, 0.0, c->stream)) != hipSuccess)
         return lbm_hip_fail(e, "lbm_init bookkeeping");

@@ -94,6 +94,7 @@ class Ensemble:
             native.check(self.lib.lbm_init(self._ctx, seed, noise_amp))
         else:
             native.check(self.lib.lbm_init_flow(self._ctx, seed, noise_amp, ux0))
+        self._active = None  # the library makes every member active again
 
     def step(self, n_steps: int) -> None:
         native.check(self.lib.lbm_step_batch(self._ctx, n_steps))
@@ -302,6 +303,20 @@ class Ensemble:
         out = torch.empty((n, 3, side, side), dtype=torch.float32, device=self.device)
         native.check(self.lib.score_features(self._ctx, m0, n, px0, py0, patch, pool, u_scale, rho_scale,
                                              _ptr(out)))
+        return out
+
+    def features_active(self, px0: int, py0: int, patch: int, pool: int, u_scale: float,
+                        rho_scale: float) -> torch.Tensor:
+        """Feature pictures of the active members, in ascending member order:
+        [n_active, 3, patch/pool, patch/pool]."""
+        side = patch // pool
+        n_act = self.n if self._active is None else sum(self._active)
+        out = torch.empty((n_act, 3, side, side), dtype=torch.float32, device=self.device)
+        rows = ctypes.c_int32()
+        native.check(self.lib.score_features_active(self._ctx, px0, py0, patch, pool, u_scale, rho_scale,
+                                                    _ptr(out), ctypes.byref(rows)))
+        if rows.value != n_act:
+            raise RuntimeError(f"the library has {rows.value} active members, the ensemble {n_act}")
         return out
 
     def perturb(self, mask: Sequence[int], key: int, period: int, eps: float, snapshots: torch.Tensor) -> None:

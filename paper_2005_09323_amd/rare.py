@@ -210,19 +210,32 @@ class AmsRunner:
         self.ckpts = torch.empty((n, t_a // ckpt_every + 1, self.state_floats), dtype=torch.float32, device=ens.device)
         self.ghat = torch.full((n, self.n_score), float("-inf"), dtype=torch.float32, device=ens.device)
         self.time = np.zeros(n, dtype=np.int64)
+        self._fcache = None  # (members, their grid columns, both on the device) of the last scatter
 
     # -- stepping ----------------------------------------------------------
     def _features(self, members: Sequence[int], times: np.ndarray) -> None:
-        """Network scores of `members` at their current times: one feature pass and one forward
-        pass over the ensemble, one scatter into the score grid."""
+        """Network scores of `members` (the active members) at their current times: one feature
+        pass and one forward pass over the active members only, one scatter into the score grid.
+
+        The scatter's row and column indices stay on the device while the active set is the same
+        (its members step together, so every column moves by the same count): a stride copies
+        nothing from the host and never waits for the device."""
         if self.net is None:
             return
-        f = self.ens.features(0, self.ens.n, **self.fargs)
+        order = sorted(members)
+        cols = times[order] // self.stride - 1
+        c = self._fcache
+        if c is None or c[0] != tuple(order) or np.any(cols - c[1] != cols[0] - c[1][0]):
+            dev = self.ghat.device
+            idx = torch.as_tensor(order, dtype=torch.long).pin_memory().to(dev, non_blocking=True)
+            col = torch.as_tensor(cols, dtype=torch.long).pin_memory().to(dev, non_blocking=True)
+            self._fcache = c = (tuple(order), cols.copy(), idx, col)
+        f = self.ens.features_active(**self.fargs)  # rows in ascending member order
+        if f.shape[0] != len(order):
+            raise RuntimeError("the ensemble's active members differ from the members being scored")
         step = self.net.max_batch
         y = torch.cat([self.net.forward(f[b:b + step]) for b in range(0, f.shape[0], step)])
-        idx = torch.as_tensor(list(members), dtype=torch.long, device=self.ghat.device)
-        col = torch.as_tensor(times[list(members)] // self.stride - 1, dtype=torch.long, device=self.ghat.device)
-        self.ghat[idx, col] = y[idx]
+        self.ghat.index_put_((c[2], c[3] + int(cols[0] - c[1][0])), y)
 
     def _advance(self, members: Sequence[int], perturb_at: dict, period: int) -> int:
         """Run `members` from their times to t_a on the stride grid; returns member-steps.

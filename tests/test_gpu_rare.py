@@ -348,6 +348,48 @@ def test_ams_branch_without_perturbation_replays_parent_exactly():
     assert res.member_steps > 6 * 96
 
 
+def test_learned_ams_scores_active_members_only_bit_identical():
+    """The learned-score AMS path scores only the members it steps (one feature and one forward
+    pass over the active members, device-side scatter indices): bit-identical to scoring every
+    member and scattering the active rows, over a run with replays, perturbations and members
+    finishing at different times."""
+    from paper_2005_09323_amd import rare
+    from paper_2005_09323_amd.ensemble import ScoreNet
+
+    class AllMembers(rare.AmsRunner):
+        def _features(self, members, times):
+            f = self.ens.features(0, self.ens.n, **self.fargs)
+            y = self.net.forward(f)
+            idx = torch.as_tensor(list(members), dtype=torch.long, device=self.ghat.device)
+            col = torch.as_tensor(times[list(members)] // self.stride - 1, dtype=torch.long,
+                                  device=self.ghat.device)
+            self.ghat[idx, col] = y[idx]
+
+    p = workloads.cnn_params(4)
+    flat = np.concatenate([np.ravel(p[k]) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4")])
+    n, t_a, stride, ckpt = 7, 96, 8, 32
+    m = workloads.Member(64, 16, 0.6, 2e-5, (20, 5, 4))
+    snaps = torch.from_numpy(workloads.snapshot_states(3, m, 5)).cuda()
+    fa = dict(px0=24, py0=0, patch=16, pool=1, u_scale=20.0, rho_scale=200.0)
+    out = []
+    for cls in (rare.AmsRunner, AllMembers):
+        ens = _ens([m] * n, cap=t_a + 1)
+        ens.init(31, 1e-2)
+        net = ScoreNet(torch.from_numpy(flat.astype(np.float32)), n)
+        runner = cls(ens, t_a, window=16, stride=stride, ckpt_every=ckpt, key=29, eps=0.01, snapshots=snaps,
+                     net=net, feature_args=fa, target=0.5, width=0.1)
+        res = runner.run(n_kill=2, max_iter=4, threshold=1e9)
+        out.append((res.k_history, res.member_steps, runner.ghat.cpu().numpy(), ens.series[:, :t_a + 1].cpu().numpy(),
+                    res.score_max))
+        ens.close()
+    (k_a, s_a, g_a, d_a, x_a), (k_b, s_b, g_b, d_b, x_b) = out
+    assert len(k_a) == 4 and k_a == k_b and s_a == s_b
+    assert np.isfinite(g_a[:, 0]).all()
+    np.testing.assert_array_equal(g_a, g_b)
+    np.testing.assert_array_equal(d_a, d_b)
+    np.testing.assert_array_equal(x_a, x_b)
+
+
 def test_ams_on_lbm_matches_oracle_ams():
     """Device AMS (checkpoints, replay, perturbation, selection) vs the oracle's AMS re-simulating
     with the oracle LBM from stored states."""

@@ -235,6 +235,41 @@ def test_features_match_oracle():
         assert np.abs(got[i] - ref).max() <= 1e-6 * np.abs(ref).max() + 1e-9
 
 
+def test_features_of_active_members_match_member_range():
+    """score_features_active gives the rows of score_features for the active members, in
+    ascending member order, bit for bit: every member at first, a subset under a mask, every
+    member again after a NULL mask and after lbm_init; no rows for an empty mask; a patch
+    outside an active member is rejected."""
+    from paper_2005_09323_amd import native
+    from paper_2005_09323_amd.ensemble import Ensemble
+    m = workloads.Member(64, 32, 0.6, 1e-5, (20, 12, 6))
+    n = 9
+    ens = Ensemble([m] * n, series_capacity=40)
+    ens.init(5, 1e-2, ux0=0.03)
+    ens.step(7)
+    fa = dict(px0=24, py0=0, patch=32, pool=2, u_scale=20.0, rho_scale=200.0)
+    full = ens.features(0, n, **fa)
+    assert torch.equal(ens.features_active(**fa), full)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        mask = (rng.random(n) < 0.5).astype(int)
+        mask[rng.integers(n)] = 1
+        ens.set_active(mask.tolist())
+        got = ens.features_active(**fa)
+        assert torch.equal(got, full[torch.from_numpy(np.flatnonzero(mask)).cuda()])
+    ens.set_active([0] * n)
+    assert ens.features_active(**fa).shape[0] == 0
+    ens.set_active(None)
+    assert torch.equal(ens.features_active(**fa), full)
+    ens.set_active([1] + [0] * (n - 1))
+    ens.init(5, 1e-2, ux0=0.03)  # every member active again, the same states as at the start
+    ens.step(7)
+    assert torch.equal(ens.features_active(**fa), full)
+    with pytest.raises(native.LbmError):
+        ens.features_active(px0=40, py0=0, patch=32, pool=2, u_scale=1.0, rho_scale=1.0)
+    ens.close()
+
+
 def test_learned_score_predicts_future_drag_better_than_plain_score():
     """What the trained network gains over the method without it: on the stationary channel flow
     (128 members of 512 x 128 after the burn-in), the network's validation R^2 for the next
