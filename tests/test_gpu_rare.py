@@ -47,8 +47,11 @@ def _full(dev32, ch):
     return f
 
 
-@pytest.mark.parametrize("n,n_bad,k,seed", [(64, 0, 1.5, 1), (64, 7, 0.3, 2), (256, 3, 4.0, 3), (1000, 0, 1.0, 4)])
+@pytest.mark.parametrize("n,n_bad,k,seed", [(64, 0, 1.5, 1), (64, 7, 0.3, 2), (256, 3, 4.0, 3), (1000, 0, 1.0, 4),
+                                            (4096, 17, 0.7, 5), (1, 0, 1.0, 6)])
 def test_gktl_selection_matches_oracle(n, n_bad, k, seed):
+    """Ancestors exactly and ln R to 1e-13 against the oracle, up to the largest ensemble one
+    selection handles (4096 members) and down to a single member."""
     m = workloads.Member(8, 4, 0.6, 0.0, None)
     ens = _ens([m] * n)
     ens.init(0, 0.0)
@@ -61,6 +64,16 @@ def test_gktl_selection_matches_oracle(n, n_bad, k, seed):
         assert np.array_equal(anc.cpu().numpy(), ref)
         assert math.isclose(lnr.item(), ogktl.log_normaliser(k * accum_used), rel_tol=1e-13, abs_tol=1e-13)
         assert torch.count_nonzero(ens.accum) == 0
+
+
+def test_ensemble_beyond_the_selections_largest_is_rejected():
+    """An ensemble holds at most the 4096 members one selection handles: a larger one is
+    refused at creation."""
+    from paper_2005_09323_amd import native
+    m = workloads.Member(8, 4, 0.6, 0.0, None)
+    with pytest.raises(native.LbmError) as e:
+        _ens([m] * 4097)
+    assert e.value.code == native.LBM_EINVAL
 
 
 def test_gktl_all_nonfinite_is_rejected_and_changes_nothing():
