@@ -162,7 +162,8 @@ int lbm_set_graphs(lbm_ctx* ctx, int32_t on);
    the obstacle; here by momentum exchange, see the conventions above) of steps
    t0 .. t1-1 of every member: copies drag columns [t0, t1) into out_dev
    (device float[n][t1-t0], row m = member m), enqueued on the context's
-   stream.  LBM_EINVAL unless 0 <= t0 <= t1 <= series_capacity. */
+   stream.  LBM_EINVAL unless 0 <= t0 <= t1 <= series_capacity; out_dev may
+   be NULL when t0 == t1 (nothing is copied). */
 int lbm_drag(const lbm_ctx* ctx, int32_t t0, int32_t t1, float* out_dev);
 
 /* Device pointer to member m's current state ([9][ny][nx] deviations). */

@@ -576,9 +576,10 @@ extern "C" int lbm_set_graphs(lbm_ctx* c, int32_t on) {
 }
 
 extern "C" int lbm_drag(const lbm_ctx* c, int32_t t0, int32_t t1, float* out_dev) {
-    if (!c || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     if (t0 < 0 || t1 < t0 || t1 > c->cap) return lbm_fail(LBM_EINVAL, "bad column range [%d, %d)", t0, t1);
     if (t1 == t0) return LBM_OK;
+    if (!out_dev) return lbm_fail(LBM_EINVAL, "NULL output");
     hipError_t e = hipMemcpy2DAsync(out_dev, sizeof(float) * (t1 - t0), c->series + t0, sizeof(float) * c->cap,
                                     sizeof(float) * (t1 - t0), c->n, hipMemcpyDeviceToDevice, c->stream);
     return e == hipSuccess ? LBM_OK : lbm_hip_fail(e, "drag copy");

@@ -418,6 +418,9 @@ def test_capacity_and_argument_errors():
     ens.set_time(1)
     ens.step(3)
     assert ens.time() == 4
+    assert ens.drag(2, 2).shape == (1, 0)  # an empty column range copies nothing
+    with pytest.raises(native.LbmError):
+        ens.drag(0, 11)  # beyond the series capacity
 
 
 def test_init_with_uniform_velocity_matches_oracle():
