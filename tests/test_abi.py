@@ -81,3 +81,25 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lbm_drag(None, 0, 1, None) == native.LBM_EINVAL
     assert lib.lbm_destroy(None) == native.LBM_OK
     assert lib.lbm_tile_count() >= 4
+
+
+def test_size_limits_are_refused_on_the_host():
+    """Every size limit is checked before any device work (the pointers below are never
+    dereferenced): ensembles above 4096 members, AMS selections outside 1..2048 series,
+    estimator sizes and ranges; empty estimator calls succeed without buffers."""
+    lib = native.lib()
+    m = workloads.Member(64, 4, 0.6, 0.0, None)
+    rc, err = _create([m] * 4097)
+    assert rc == native.LBM_EINVAL and "4096" in err
+    p = 0x1000
+    for n in (0, 2049):
+        assert lib.ams_score_kill_branch(p, n, 10, 1, 1, 0, p, p, p, p, p, p, None) == native.LBM_EINVAL
+    assert lib.ams_score_kill_branch(p, 8, 0, 1, 1, 0, p, p, p, p, p, p, None) == native.LBM_EINVAL
+    assert lib.gktl_scgf(p, 0, 1.0, p, None) == native.LBM_EINVAL
+    assert lib.gktl_scgf(p, 3, 0.0, p, None) == native.LBM_EINVAL
+    assert lib.gktl_scgf(p, 3, float("inf"), p, None) == native.LBM_EINVAL
+    assert lib.return_times(p, 4, 100.0, 100.0, p, None) == native.LBM_EINVAL
+    assert lib.return_times(p, -1, 100.0, 10.0, p, None) == native.LBM_EINVAL
+    assert lib.return_times(None, 0, 100.0, 10.0, None, None) == native.LBM_OK
+    assert lib.ams_probability(p, 3, 0, p, p, 1, p, None) == native.LBM_EINVAL
+    assert lib.ams_probability(None, 0, 8, None, None, 0, None, None) == native.LBM_OK
