@@ -177,19 +177,19 @@ __device__ __forceinline__ double cm_guo(const MemberDev& m, float d[9], unsigne
 // post-collision raw moments follow by the binomial shift and the
 // populations by the inverse moment matrix, all as deviations from the rest
 // state (the weights' moments 1, 1/3, 1/3, 1/9 subtracted analytically, so a
-// state at rest stays exactly at rest).  Equal to cm_guo with those rates up
-// to FP64 rounding; contraction pinned as there.
+// state at rest stays exactly at rest).  The shift's terms in rho u^n and
+// F u^n cancel against those of the third- and fourth-order moments, and the
+// pre-collision second moments about u use j_x = rho u_x - F/2, j_y = rho u_y,
+// so each raw moment is a short sum.  Equal to cm_guo with those rates up to
+// FP64 rounding; contraction pinned as there.
 __device__ __forceinline__ double cm1_guo(const MemberDev& m, float d[9], unsigned links) {
 #pragma clang fp contract(on)
     const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
     const double d5 = d[5], d6 = d[6], d7 = d[7], d8 = d[8];
     const double dr = ((d0 + d1) + (d2 + d3)) + ((d4 + d5) + (d6 + d7)) + d8;  // rho - 1
-    const double diag = (d5 + d6) + (d7 + d8);
     const double rho = 1.0 + dr;
     const double jx = ((d1 - d3) + (d5 - d6)) + (d8 - d7);
     const double jy = ((d2 - d4) + (d5 - d7)) + (d6 - d8);
-    const double dm20 = (d1 + d3) + diag;  // m20 - 1/3
-    const double dm02 = (d2 + d4) + diag;  // m02 - 1/3
     const double m11 = (d5 - d6) + (d7 - d8);
     double inv = (double)__builtin_amdgcn_rcpf((float)rho);
     inv = inv * (2.0 - rho * inv);
@@ -198,25 +198,23 @@ __device__ __forceinline__ double cm1_guo(const MemberDev& m, float d[9], unsign
     const double ux = (jx + m.half_fx) * inv, uy = jy * inv;
     const double uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
     // second order: k20 - k02 and k11 relax at omega, k20 + k02 goes to 2 rho / 3
-    const double kd = ((dm20 - dm02) - 2.0 * ux * jx + 2.0 * uy * jy) + (uxx - uyy) * rho;
-    const double k11 = m11 - ux * jy - uy * jx + uxy * rho;
+    // (m20 - m02 = (d1 + d3) - (d2 + d4): the diagonal directions and the weights cancel)
+    const double kd = (((d1 + d3) - (d2 + d4)) - rho * (uxx - uyy)) + ux * F;
+    const double k11 = (m11 - rho * uxy) + 0.5 * F * uy;
     const double om1 = 1.0 - m.omega;
     const double a = 0.5 * om1 * kd;
     const double k11s = om1 * k11;
     const double k20s = rho * (1.0 / 3.0) + a, k02s = rho * (1.0 / 3.0) - a;
-    // third and fourth order: equilibrium plus (1/2) of the source's central moments
-    const double k21s = -(rho * uxx * uy + uxy * F);
-    const double k12s = 0.5 * F * ((1.0 / 3.0) - uyy) - rho * ux * uyy;
-    const double dk22s = dr * (1.0 / 9.0) + 3.0 * rho * uxx * uyy + 2.0 * ux * uyy * F;  // k22* - 1/9
-    // post-collision raw moments (k10* = F/2, k01* = 0), as deviations from rest
+    // post-collision raw moments (k10* = F/2, k01* = 0), as deviations from rest; the third
+    // and fourth central moments (equilibrium plus half the source's) enter only through
+    // what survives the shift
     const double m10s = jx + F;
     const double dm20s = dr * (1.0 / 3.0) + a + ux * F + uxx * rho;
     const double dm02s = dr * (1.0 / 3.0) - a + uyy * rho;
     const double m11s = k11s + 0.5 * uy * F + uxy * rho;
-    const double m21s = k21s + 2.0 * ux * k11s + uy * k20s + uxy * F + uxx * uy * rho;
-    const double m12s = k12s + 2.0 * uy * k11s + ux * k02s + 0.5 * uyy * F + ux * uyy * rho;
-    const double dm22s = (dk22s + 2.0 * ux * k12s + 2.0 * uy * k21s) + (uxx * k02s + uyy * k20s + 4.0 * uxy * k11s) +
-                         (ux * uyy * F + uxx * uyy * rho);
+    const double m21s = 2.0 * ux * k11s + uy * k20s;
+    const double m12s = F * (1.0 / 6.0) + 2.0 * uy * k11s + ux * k02s;
+    const double dm22s = (dr * (1.0 / 9.0) + ux * F * (1.0 / 3.0)) + (uxx * k02s + uyy * k20s + 4.0 * uxy * k11s);
     // populations (inverse of the raw-moment matrix)
     const double o0 = (dr - dm20s) - (dm02s - dm22s);
     const double o1 = 0.5 * ((m10s + dm20s) - (m12s + dm22s));
