@@ -215,16 +215,16 @@ __device__ __forceinline__ double cm1_guo(const MemberDev& m, float d[9], unsign
     const double m21s = 2.0 * ux * k11s + uy * k20s;
     const double m12s = F * (1.0 / 6.0) + 2.0 * uy * k11s + ux * k02s;
     const double dm22s = (dr * (1.0 / 9.0) + ux * F * (1.0 / 3.0)) + (uxx * k02s + uyy * k20s + 4.0 * uxy * k11s);
-    // populations (inverse of the raw-moment matrix)
-    const double o0 = (dr - dm20s) - (dm02s - dm22s);
-    const double o1 = 0.5 * ((m10s + dm20s) - (m12s + dm22s));
-    const double o3 = 0.5 * ((dm20s - m10s) + (m12s - dm22s));
-    const double o2 = 0.5 * ((jy + dm02s) - (m21s + dm22s));
-    const double o4 = 0.5 * ((dm02s - jy) + (m21s - dm22s));
-    const double o5 = 0.25 * ((m11s + m21s) + (m12s + dm22s));
-    const double o6 = 0.25 * ((m21s - m11s) + (dm22s - m12s));
-    const double o7 = 0.25 * ((m11s - m21s) + (dm22s - m12s));
-    const double o8 = 0.25 * ((m12s - m11s) + (dm22s - m21s));
+    // populations (inverse of the raw-moment matrix), opposite directions as sum and
+    // difference of shared terms
+    const double ax = dm20s - dm22s, bx = m10s - m12s;  // f1 + f3 and f1 - f3 (deviations)
+    const double ay = dm02s - dm22s, by = jy - m21s;    // f2 + f4 and f2 - f4
+    const double t1 = dm22s + m12s, t2 = dm22s - m12s, t3 = m11s + m21s, t4 = m21s - m11s;
+    const double o0 = (dr - dm20s) - ay;
+    const double o1 = 0.5 * (ax + bx), o3 = 0.5 * (ax - bx);
+    const double o2 = 0.5 * (ay + by), o4 = 0.5 * (ay - by);
+    const double o5 = 0.25 * (t1 + t3), o8 = 0.25 * (t1 - t3);
+    const double o6 = 0.25 * (t2 + t4), o7 = 0.25 * (t2 - t4);
     double drag = 0.0;
     if (links) {
         if ((links >> 1) & 1u) drag += 2.0 * o1;
