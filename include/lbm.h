@@ -546,15 +546,16 @@ int score_features(const lbm_ctx* ctx, int32_t m0, int32_t n, int32_t px0, int32
  * lbm_set_active; every member before any mask is set, after lbm_init and
  * after a NULL mask): row r of out_dev is the r-th active member in
  * ascending member order, with the same arithmetic as score_features.  The
- * number of rows (the active count) goes to *n_rows (host, may be NULL).
- * out_dev: device float[n_active][3][patch/pool][patch/pool] (may be NULL
- * when no member is active).  The patch must lie inside every active member,
- * else LBM_EINVAL and nothing is written.
+ * number of rows (the active count) goes to *n_rows (host, may be NULL),
+ * also when the call fails.  out_dev: device float[max_rows][3][patch/pool]
+ * [patch/pool] (may be NULL when no member is active).  LBM_EINVAL, with
+ * nothing written, when more than max_rows members are active or the patch
+ * does not lie inside every active member.
  * Async on the ensemble's stream; reads the mask the last lbm_set_active
  * queued on it.
  */
 int score_features_active(const lbm_ctx* ctx, int32_t px0, int32_t py0, int32_t patch, int32_t pool,
-                          double u_scale, double rho_scale, float* out_dev, int32_t* n_rows);
+                          double u_scale, double rho_scale, float* out_dev, int32_t max_rows, int32_t* n_rows);
 
 /* y_dev[b] = network(x_dev[b]) for a batch of device float[batch][3][16][16]. */
 int score_net_forward(const float* params_dev, const float* x_dev, int32_t batch, float* y_dev,

@@ -110,10 +110,14 @@ extern "C" int score_features(const lbm_ctx* c, int32_t m0, int32_t n, int32_t p
 }
 
 extern "C" int score_features_active(const lbm_ctx* c, int32_t px0, int32_t py0, int32_t patch, int32_t pool,
-                                     double u_scale, double rho_scale, float* out_dev, int32_t* n_rows) {
+                                     double u_scale, double rho_scale, float* out_dev, int32_t max_rows,
+                                     int32_t* n_rows) {
     if (!c) return lbm_fail(LBM_EINVAL, "NULL context");
     if (pool < 1 || patch < pool || patch % pool || patch / pool > 16)
         return lbm_fail(LBM_EINVAL, "patch must be a multiple of pool with patch/pool <= 16");
+    if (n_rows) *n_rows = c->n_active;
+    if (c->n_active > max_rows)
+        return lbm_fail(LBM_EINVAL, "%d active members, the output holds %d rows", c->n_active, max_rows);
     if (c->n_active > 0 && !out_dev) return lbm_fail(LBM_EINVAL, "NULL output");
     for (int m = 0; m < c->n; ++m) {
         if (!c->h_active[m]) continue;
@@ -121,7 +125,6 @@ extern "C" int score_features_active(const lbm_ctx* c, int32_t px0, int32_t py0,
         if (px0 < 0 || py0 < 0 || px0 + patch > d.nx || py0 + patch > d.ny)
             return lbm_fail(LBM_EINVAL, "patch outside member %d", m);
     }
-    if (n_rows) *n_rows = c->n_active;
     if (c->n_active == 0) return LBM_OK;
     FeatureArgs a;
     a.members = c->d_members;

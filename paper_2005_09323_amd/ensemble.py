@@ -314,7 +314,7 @@ class Ensemble:
         out = torch.empty((n_act, 3, side, side), dtype=torch.float32, device=self.device)
         rows = ctypes.c_int32()
         native.check(self.lib.score_features_active(self._ctx, px0, py0, patch, pool, u_scale, rho_scale,
-                                                    _ptr(out), ctypes.byref(rows)))
+                                                    _ptr(out), n_act, ctypes.byref(rows)))
         if rows.value != n_act:
             raise RuntimeError(f"the library has {rows.value} active members, the ensemble {n_act}")
         return out

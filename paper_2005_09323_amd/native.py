@@ -82,7 +82,7 @@ _SIG = {
     "score_net_params": (_I, []),
     "score_net_workspace_bytes": (ctypes.c_size_t, [_I]),
     "score_features": (ctypes.c_int, [_P, _I, _I, _I, _I, _I, _I, _D, _D, _P]),
-    "score_features_active": (ctypes.c_int, [_P, _I, _I, _I, _I, _D, _D, _P, _P]),
+    "score_features_active": (ctypes.c_int, [_P, _I, _I, _I, _I, _D, _D, _P, _I, _P]),
     "score_net_forward": (ctypes.c_int, [_P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "score_net_grad": (ctypes.c_int, [_P, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
     "score_net_grad_noalloc": (ctypes.c_int, [_P, _P, _P, _I, _P, _P, _P]),

@@ -173,7 +173,7 @@ static void check_null_context() {
     CHECK(lbm_copy_state_out(nullptr, 0, f) == LBM_EINVAL);
     CHECK(lbm_copy_state_in(nullptr, 0, f, 0) == LBM_EINVAL);
     CHECK(score_features(nullptr, 0, 1, 0, 0, 64, 4, 1.0, 1.0, f) == LBM_EINVAL);
-    CHECK(score_features_active(nullptr, 0, 0, 64, 4, 1.0, 1.0, f, &i32) == LBM_EINVAL);
+    CHECK(score_features_active(nullptr, 0, 0, 64, 4, 1.0, 1.0, f, 1, &i32) == LBM_EINVAL);
     CHECK(lbm_tile_count() >= 4);
 }
 

@@ -267,6 +267,14 @@ def test_features_of_active_members_match_member_range():
     assert torch.equal(ens.features_active(**fa), full)
     with pytest.raises(native.LbmError):
         ens.features_active(px0=40, py0=0, patch=32, pool=2, u_scale=1.0, rho_scale=1.0)
+    # an output with fewer rows than active members is refused before any write
+    import ctypes
+    small = torch.full((n - 1, 3, 16, 16), 7.0, device="cuda")
+    rows = ctypes.c_int32()
+    rc = native.lib().score_features_active(ens._ctx, 24, 0, 32, 2, 20.0, 200.0, small.data_ptr(), n - 1,
+                                            ctypes.byref(rows))
+    assert rc == native.LBM_EINVAL and rows.value == n
+    assert bool((small == 7.0).all())
     ens.close()
 
 
