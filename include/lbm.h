@@ -77,7 +77,7 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* One trajectory: lattice size, obstacle, relaxation time and body force. */
 typedef struct {
-    int32_t nx, ny;            /* lattice cells; nx >= 4, ny >= 4 */
+    int32_t nx, ny;            /* lattice cells; nx >= 4, ny >= 4, 9 nx ny < 2^32 */
     int32_t sq_x0, sq_y0;      /* lower-left solid cell of the square */
     int32_t sq_side;           /* side s in cells, 0 = no obstacle */
     int32_t reserved;          /* must be 0 */

@@ -104,7 +104,9 @@ extern "C" size_t lbm_state_floats(const lbm_member_desc* members, int32_t n) {
 
 static int validate_member(const lbm_member_desc& d, int i) {
     if (d.nx < 4 || d.ny < 4) return lbm_fail(LBM_EINVAL, "member %d: nx, ny must be >= 4", i);
-    if ((long long)d.nx * d.ny > (1LL << 30)) return lbm_fail(LBM_EINVAL, "member %d: lattice too large", i);
+    // the kernels index a member's 9 planes with 32-bit element offsets
+    if (9LL * d.nx * d.ny > 0xFFFFFFFFLL)
+        return lbm_fail(LBM_EINVAL, "member %d: lattice too large (at most %lld cells)", i, 0xFFFFFFFFLL / 9);
     if (d.reserved != 0) return lbm_fail(LBM_EINVAL, "member %d: reserved field must be 0", i);
     if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return lbm_fail(LBM_EINVAL, "member %d: tau must be > 1/2", i);
     if (!std::isfinite(d.force_x)) return lbm_fail(LBM_EINVAL, "member %d: force must be finite", i);

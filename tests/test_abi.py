@@ -103,3 +103,14 @@ def test_size_limits_are_refused_on_the_host():
     assert lib.return_times(None, 0, 100.0, 10.0, None, None) == native.LBM_OK
     assert lib.ams_probability(p, 3, 0, p, p, 1, p, None) == native.LBM_EINVAL
     assert lib.ams_probability(None, 0, 8, None, None, 0, None, None) == native.LBM_OK
+
+
+def test_member_size_limit_follows_32_bit_plane_offsets():
+    """A member's 9 populations are indexed with 32-bit element offsets: 477,218,588 cells is
+    the largest lattice accepted (the buffers below are then too small, a different error)."""
+    big = workloads.Member(32768, 14564, 0.6, 0.0, None)   # 477,233,152 cells
+    rc, err = _create([big])
+    assert rc == native.LBM_EINVAL and "too large" in err
+    ok = workloads.Member(32768, 14563, 0.6, 0.0, None)    # 477,200,384 cells
+    rc, err = _create([ok])
+    assert rc == native.LBM_EINVAL and "too large" not in err
