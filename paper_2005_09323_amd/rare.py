@@ -210,7 +210,7 @@ class AmsRunner:
         self.ckpts = torch.empty((n, t_a // ckpt_every + 1, self.state_floats), dtype=torch.float32, device=ens.device)
         self.ghat = torch.full((n, self.n_score), float("-inf"), dtype=torch.float32, device=ens.device)
         self.time = np.zeros(n, dtype=np.int64)
-        self._fcache = None  # (members, their grid columns, both on the device) of the last scatter
+        self._fcache = None  # (members, their grid columns, their flat grid positions on the device)
 
     # -- stepping ----------------------------------------------------------
     def _features(self, members: Sequence[int], times: np.ndarray) -> None:
@@ -225,17 +225,21 @@ class AmsRunner:
         order = sorted(members)
         cols = times[order] // self.stride - 1
         c = self._fcache
-        if c is None or c[0] != tuple(order) or np.any(cols - c[1] != cols[0] - c[1][0]):
-            dev = self.ghat.device
-            idx = torch.as_tensor(order, dtype=torch.long).pin_memory().to(dev, non_blocking=True)
-            col = torch.as_tensor(cols, dtype=torch.long).pin_memory().to(dev, non_blocking=True)
-            self._fcache = c = (tuple(order), cols.copy(), idx, col)
+        if (c is None or c[0] != tuple(order) or cols[0] < c[1][0]
+                or np.any(cols - c[1] != cols[0] - c[1][0])):
+            # flat positions in the score grid at the columns of this moment
+            flat = np.asarray(order, dtype=np.int64) * self.n_score + cols
+            pos = torch.as_tensor(flat).pin_memory().to(self.ghat.device, non_blocking=True)
+            self._fcache = c = (tuple(order), cols.copy(), pos)
         f = self.ens.features_active(**self.fargs)  # rows in ascending member order
         if f.shape[0] != len(order):
             raise RuntimeError("the ensemble's active members differ from the members being scored")
         step = self.net.max_batch
-        y = torch.cat([self.net.forward(f[b:b + step]) for b in range(0, f.shape[0], step)])
-        self.ghat.index_put_((c[2], c[3] + int(cols[0] - c[1][0])), y)
+        y = (self.net.forward(f) if f.shape[0] <= step else
+             torch.cat([self.net.forward(f[b:b + step]) for b in range(0, f.shape[0], step)]))
+        # every column has moved on by the same count since the positions were made: index the
+        # flat grid from that offset (a view, no kernel) rather than adding it to the positions
+        self.ghat.view(-1)[int(cols[0] - c[1][0]):].index_put_((c[2],), y)
 
     def _advance(self, members: Sequence[int], perturb_at: dict, period: int) -> int:
         """Run `members` from their times to t_a on the stride grid; returns member-steps.
