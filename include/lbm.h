@@ -531,6 +531,8 @@ int32_t score_net_params(void);
 size_t score_net_workspace_bytes(int32_t batch);
 
 /*
+ * Input pictures of the learned AMS score (the score function of Section 4.1
+ * learned from the flow state, as the Conclusion proposes).
  * Features of members m0 .. m0+n-1 from their current states: u_x * u_scale,
  * u_y * u_scale and (rho - 1) * rho_scale averaged over pool x pool blocks of
  * the patch x patch cells whose lower-left cell is (px0, py0); rho and u are
@@ -542,12 +544,13 @@ int score_features(const lbm_ctx* ctx, int32_t m0, int32_t n, int32_t px0, int32
                    int32_t pool, double u_scale, double rho_scale, float* out_dev);
 
 /*
- * score_features for the members the ensemble currently steps (the mask of
+ * score_features for the members the ensemble currently steps (AMS scores the
+ * trajectories it re-simulates after a branching, Appendix B.1; the mask of
  * lbm_set_active; every member before any mask is set, after lbm_init and
  * after a NULL mask): row r of out_dev is the r-th active member in
  * ascending member order, with the same arithmetic as score_features.  The
  * number of rows (the active count) goes to *n_rows (host, may be NULL),
- * also when the call fails.  out_dev: device float[max_rows][3][patch/pool]
+ * also when the output is too small.  out_dev: device float[max_rows][3][patch/pool]
  * [patch/pool] (may be NULL when no member is active).  LBM_EINVAL, with
  * nothing written, when more than max_rows members are active or the patch
  * does not lie inside every active member.
